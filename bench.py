@@ -1,0 +1,199 @@
+#!/usr/bin/env python3
+"""TDoA throughput of the FCC path on one MI355X.
+
+One step = the whole hot path over the 60 s, 16-microphone recording
+(5 cm-radius circle, fs 16 kHz, N 512, hop 128: 7497 frames x 120 pairs):
+audio already in HBM -> windowed real DFT + per-mic PHAT -> pairs, fold,
+projection on the rank-D even/odd bases, expansion to the 11 lags, argmax ->
+int32 TDoA in HBM.
+
+Prints one JSON line (rank 0).  `value` is pair-frames per second.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "TDoA pair-frames/s at M=16,N=512 (mixed-prec FCC vs FP32); % HBM peak"
+
+
+def parse_args():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--precision", default="fp16", choices=["fp32", "bf16", "fp16", "fp8"])
+    ap.add_argument("--rank", type=int, default=11)
+    ap.add_argument("--no-sweep", action="store_true", help="skip the precision/rank/method sweep")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--seed", type=int, default=2000)
+    return ap.parse_args()
+
+
+def time_loop(torch, fn, steps):
+    """Average milliseconds of fn() over `steps` launches, HIP events on the
+    current stream (the stream every library call is enqueued on)."""
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(steps):
+        fn()
+    stop.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / steps
+
+
+def kernel_bytes(plan, L, T):
+    """Algorithmic HBM bytes of one launch of each kernel."""
+    esz = plan.info.spectrum_elem_bytes
+    spec = T * plan.M * plan.F * esz
+    return {
+        "stft_phat": plan.M * L * 4 + spec,              # audio once + spectra written
+        "pair": spec + T * plan.P * 4,                   # spectra once + TDoA written
+    }
+
+
+def traffic_for(kernel_file: str, workload: str, precision: str, rank: int):
+    """Counter-measured HBM bytes per launch, if the committed record still
+    matches the kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    src = os.path.join(ROOT, "paper_2204_13622_amd", "csrc", kernel_file)
+    if not os.path.exists(src):
+        return None
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    for r in rec.get("records", []):
+        if (r.get("kernel_file") == kernel_file and r.get("source_sha256") == digest
+                and r.get("workload") == workload and r.get("precision") == precision
+                and r.get("rank") == rank):
+            return r.get("bytes_per_launch")
+    return None
+
+
+def cpu_baseline(rec, tau_max, D, budget_s):
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+    import oracle.fcc_oracle as O
+    T = (rec.L - rec.N) // rec.hop + 1
+    P = rec.M * (rec.M - 1) // 2
+    with threadpool_limits(1):
+        B = O.fcc_basis(rec.N, tau_max, D)
+        t0 = time.perf_counter()
+        O.fcc_tdoa(rec.x, rec.N, rec.hop, tau_max, D, frames=np.arange(32), basis=B)
+        per_frame = (time.perf_counter() - t0) / 32
+        n = int(min(T, max(64, budget_s / max(per_frame, 1e-6))))
+        frames = np.arange(n)
+        t0 = time.perf_counter()
+        O.fcc_tdoa(rec.x, rec.N, rec.hop, tau_max, D, frames=frames, basis=B)
+        dt = time.perf_counter() - t0
+    return {"value": n * P / dt, "unit": "pair-frames/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n} of {T} frames x {P} pairs of the benchmark recording, "
+                      f"FP64 NumPy oracle fcc_tdoa (STFT, PHAT, folded projection, D={D}, argmax), "
+                      f"one thread, {dt:.1f} s"}
+
+
+def main():
+    args = parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the TDoA path is data-parallel over frames and "
+              "this build does not shard it across GPUs; run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2204_13622_amd as fcc
+    from gen import make_recording
+
+    rec = make_recording(2, seed=args.seed)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    x = torch.from_numpy(rec.x).to(dev)
+
+    def make(precision, rank, method="fcc"):
+        plan = fcc.Plan(rec.mic_xyz, rec.fs, rec.c, frame_size=rec.N, hop=rec.hop,
+                        rank=rank, precision=precision, method=method)
+        T = plan.num_frames(rec.L)
+        ws = torch.empty(plan.workspace_bytes(T), dtype=torch.uint8, device=dev)
+        out = torch.empty((T, plan.P), dtype=torch.int32, device=dev)
+        plan.basis_tensor(dev)
+        return plan, T, ws, out
+
+    plan, T, ws, out = make(args.precision, args.rank)
+    P = plan.P
+    step = lambda: plan.tdoa(x, out=out, workspace=ws)  # noqa: E731
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ms = time_loop(torch, step, args.steps)
+    value = T * P / (ms * 1e-3)
+
+    # per-kernel averages over their own timed loops (same stream)
+    spec_view = ws[:T * plan.M * plan.F * plan.info.spectrum_elem_bytes].view(
+        plan.spectrum_dtype()).view(T, plan.M, plan.F, 2)
+    ms_stft = time_loop(torch, lambda: plan.spectra(x, out=spec_view), args.steps)
+    ms_pair = time_loop(torch, lambda: plan.tdoa_from_spectra(spec_view, out=out), args.steps)
+    kb = kernel_bytes(plan, rec.L, T)
+    workload = f"M16-circle5cm-fs16k-N512-hop128-60s"
+    dom = "pair" if ms_pair >= ms_stft else "stft_phat"
+    dom_ms = ms_pair if dom == "pair" else ms_stft
+    achieved = kb[dom] / (dom_ms * 1e-3) / 1e9
+    traffic = traffic_for("pair_valu.hip" if dom == "pair" else "stft_phat.hip", workload,
+                          args.precision, args.rank)
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic,
+                "kernels_ms": {"stft_phat": round(ms_stft, 4), "pair": round(ms_pair, 4)},
+                "kernels_GBs": {"stft_phat": round(kb["stft_phat"] / ms_stft / 1e6, 1),
+                                "pair": round(kb["pair"] / ms_pair / 1e6, 1)}}
+
+    sweep = []
+    if not args.no_sweep:
+        for prec, rank, method in [("fp32", 6, "fcc"), ("fp32", 11, "fcc"), ("bf16", 6, "fcc"),
+                                   ("bf16", 11, "fcc"), ("fp16", 6, "fcc"), ("fp16", 11, "fcc"),
+                                   ("fp8", 6, "fcc"), ("fp8", 11, "fcc"), ("fp32", 0, "gcc"),
+                                   ("fp16", 0, "gcc")]:
+            pl, Tq, wq, oq = make(prec, rank, method)
+            f = lambda: pl.tdoa(x, out=oq, workspace=wq)  # noqa: E731
+            f()
+            msq = time_loop(torch, f, max(5, args.steps // 5))
+            sweep.append({"method": method, "precision": prec, "rank": pl.rank,
+                          "ms": round(msq, 4), "pair_frames_per_s": round(Tq * pl.P / (msq * 1e-3))})
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(rec, plan.tau_max, plan.rank, args.cpu_seconds)
+
+    line = {
+        "metric": METRIC, "value": round(value), "unit": "pair-frames/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": args.precision, "data": "synthetic",
+        "config": {"workload": "60 s recording, M=16 mics on a 5 cm-radius circle, fs=16 kHz, "
+                               "N=512 Hann frames, hop 128, tau_max=5 (I=11 lags), AR(2) gated source, "
+                               "FIR reverb RT60 0.3 s, sensor noise SNR 0-20 dB",
+                   "frames": T, "pairs": P, "pair_frames": T * P, "rank": plan.rank,
+                   "precision": args.precision, "method": "fcc"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "sweep": sweep,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

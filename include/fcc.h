@@ -1,0 +1,184 @@
+/*
+ * fcc.h - C ABI of the MI355X (gfx950) Fast Cross-Correlation TDoA library.
+ *
+ * Method: F. Grondin et al., "Fast Cross-Correlation for TDoA Estimation on
+ * Small Aperture Microphone Arrays", arXiv 2204.13622.  For every STFT frame
+ * and every microphone pair the library forms the PHAT-weighted
+ * cross-spectrum (Sec. 2, eq. 1 with alpha = 1), projects it on the cropped
+ * even/odd bases of the rank-D decomposition of the frequency-to-lag matrix
+ * (Sec. 4, eqs. 5-9), expands the coefficients to the lags tau_max .. tau_max
+ * through the dictionary, and returns the argmax lag (Sec. 2).  The GCC-PHAT
+ * comparator (Sec. 3, eq. 2) shares the front end and evaluates eq. (2) at the
+ * same lags directly.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Every call returns fcc_status; FCC_OK is 0 and errors are negative.  No
+ *   C++ exception crosses this boundary.  fcc_last_error() gives a message for
+ *   the calling thread's last error.
+ * - Argument errors are detected before anything is enqueued: a call that
+ *   returns an error has launched no work.  FCC_ERR_HIP reports a failed
+ *   launch or copy; faults that happen asynchronously show up at the caller's
+ *   next synchronisation of the stream.
+ * - Pointers named d_* are device pointers on the current HIP device; the
+ *   caller allocates and owns every device buffer (sizes from
+ *   fcc_plan_query / fcc_workspace_bytes).  Calls that compute never allocate
+ *   device memory.  A plan owns only host memory.
+ * - Work is enqueued on `stream` (0 = the null stream) and the call returns
+ *   without waiting for it.
+ * - A plan is immutable after fcc_plan_create and may be used from several
+ *   threads and streams at once; workspaces must not be shared by concurrent
+ *   calls.
+ * - Microphone pairs p = 0 .. P-1, P = M (M - 1) / 2, enumerate (i, j), i < j,
+ *   in lexicographic order: (0,1), (0,2), .., (0,M-1), (1,2), ...
+ * - TDoA sign: TDoA_ij = t_i - t_j in samples.  If x_j[n] = x_i[n - d] then
+ *   the result for pair (i, j) is -d (R = X_i X_j^* of eq. 1 and the
+ *   exp(+j 2 pi f tau / N) kernel of eq. 2).
+ */
+#ifndef FCC_H_
+#define FCC_H_
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FCC_OK = 0,
+  FCC_ERR_INVALID_ARG = -1,       /* argument outside its documented range  */
+  FCC_ERR_UNSUPPORTED = -2,       /* valid per the paper, not built here     */
+  FCC_ERR_BASIS_AMBIGUOUS = -3,   /* the rank cuts a singular-value cluster  */
+  FCC_ERR_HIP = -4,               /* a HIP launch or copy failed             */
+  FCC_ERR_INTERNAL = -5
+} fcc_status;
+
+/* Storage type of the whitened spectra and of the projection operands.
+ * Accumulation, PHAT normalisation, the lag expansion and the argmax are FP32
+ * in every mode. */
+typedef enum {
+  FCC_FP32 = 0,
+  FCC_BF16 = 1,
+  FCC_FP16 = 2,
+  FCC_FP8_E4M3 = 3                /* OCP e4m3 (finite, max 448) */
+} fcc_precision;
+
+typedef enum {
+  FCC_METHOD_FCC = 0,             /* low-rank even/odd projection (Sec. 4)   */
+  FCC_METHOD_GCC = 1              /* eq. (2) evaluated at the I lags (Sec. 3) */
+} fcc_method;
+
+/* Problem statement of Sec. 2.  mic_xyz is copied by fcc_plan_create. */
+typedef struct {
+  int32_t num_mics;               /* M >= 2                                   */
+  const double* mic_xyz;          /* [M][3] metres, host memory               */
+  double fs;                      /* sample rate f_S, Hz, > 0                 */
+  double c;                       /* speed of sound, m/s, > 0                 */
+  int32_t frame_size;             /* N: power of two, 16 <= N <= 2048         */
+  int32_t hop;                    /* frame advance in samples, > 0            */
+  int32_t tau_max;                /* 0: ceil(d_max f_S / c) from mic_xyz      */
+  int32_t rank;                   /* D in [1, I]; 0 means full rank D = I     */
+  int32_t interp;                 /* r of Sec. 3; only 1 is built             */
+  float alpha;                    /* eq. (1) smoothing; only 1 is built       */
+  fcc_precision precision;
+  fcc_method method;
+} fcc_config;
+
+typedef struct fcc_plan_s* fcc_plan;
+
+typedef struct {
+  int32_t num_mics;               /* M                                        */
+  int32_t num_pairs;              /* P = M (M - 1) / 2                        */
+  int32_t frame_size;             /* N                                        */
+  int32_t hop;
+  int32_t num_bins;               /* F = N/2 + 1                              */
+  int32_t tau_max;
+  int32_t num_lags;               /* I = 2 r tau_max + 1                      */
+  int32_t rank;                   /* D (FCC) or I (GCC)                       */
+  int32_t rank_sym;               /* components symmetric about f = N/4       */
+  int32_t rank_anti;              /* components antisymmetric about f = N/4   */
+  int32_t precision;              /* fcc_precision                            */
+  int32_t method;                 /* fcc_method                               */
+  size_t basis_bytes;             /* size of the device plan buffer           */
+  size_t spectrum_bytes_per_frame;/* M * F * (complex element size)           */
+  int32_t spectrum_elem_bytes;    /* 8 (FP32), 4 (BF16/FP16), 2 (FP8)         */
+} fcc_plan_info;
+
+/* Validates the configuration and computes, on the host in FP64, everything a
+ * geometry needs (Sec. 4, Fig. 2 "computed offline"): tau_max, the lag grid,
+ * the cropped bases p_hat_k (eq. 7) and the dictionary, the analysis window
+ * and the DFT twiddles.  No device call is made.
+ * Errors: FCC_ERR_INVALID_ARG (M < 2, non-power-of-two N, hop <= 0,
+ * tau_max >= N/4, rank outside [0, I], fs or c <= 0, null pointers),
+ * FCC_ERR_UNSUPPORTED (interp != 1, alpha != 1, M > 32),
+ * FCC_ERR_BASIS_AMBIGUOUS (rank cuts a cluster of singular values closer than
+ * 1e-9 sigma_1, so the rank-D result is not unique). */
+fcc_status fcc_plan_create(const fcc_config* config, fcc_plan* out);
+
+void fcc_plan_destroy(fcc_plan plan);
+
+fcc_status fcc_plan_query(fcc_plan plan, fcc_plan_info* info);
+
+/* Copies the plan's packed tables (window, twiddles, bases, dictionary) into
+ * d_basis, a caller-owned device buffer of info.basis_bytes bytes, aligned to
+ * 256 bytes.  Enqueued on `stream`; the host tables stay owned by the plan. */
+fcc_status fcc_plan_upload(fcc_plan plan, void* d_basis, hipStream_t stream);
+
+/* Number of whole frames in num_samples samples: floor((L - N) / hop) + 1,
+ * or 0 when L < N (frame t covers samples [t hop, t hop + N)). */
+fcc_status fcc_num_frames(fcc_plan plan, int64_t num_samples, int64_t* num_frames);
+
+/* Bytes of workspace fcc_tdoa needs for num_frames frames (the whitened
+ * spectra, num_frames * info.spectrum_bytes_per_frame, rounded up to 256). */
+fcc_status fcc_workspace_bytes(fcc_plan plan, int64_t num_frames, size_t* bytes);
+
+/* Sec. 2 front end: Hann-windowed (periodic) real DFT of every frame of every
+ * microphone, each bin divided by its magnitude (per-microphone PHAT; at
+ * alpha = 1, R_ij / |R_ij| = e_i e_j^* with e = X / |X|).  A bin whose squared
+ * magnitude is below FLT_MIN becomes 0.
+ *   d_x    [M][ld] FP32 audio, row m at d_x + m * ld, L samples used, ld >= L.
+ *   d_spec [T][M][F] complex, interleaved (re, im), in the plan's precision.
+ * T = fcc_num_frames(L); T = 0 enqueues nothing. */
+fcc_status fcc_spectra(fcc_plan plan, const void* d_basis, const float* d_x,
+                       int64_t num_samples, int64_t ld, void* d_spec,
+                       hipStream_t stream);
+
+/* The whole path from audio: fcc_spectra into d_workspace, then
+ * fcc_tdoa_from_spectra.  d_tdoa is [T][P] int32 in samples (lag index minus
+ * tau_max).  d_workspace holds fcc_workspace_bytes(T) bytes. */
+fcc_status fcc_tdoa(fcc_plan plan, const void* d_basis, const float* d_x,
+                    int64_t num_samples, int64_t ld, int32_t* d_tdoa,
+                    void* d_workspace, hipStream_t stream);
+
+/* Pairs, fold (eq. 8), projection (eq. 9), expansion 2 Re{U z} to the I lags
+ * and argmax (first index on ties), from whitened spectra laid out as
+ * fcc_spectra writes them.  With method GCC, eq. (2) at the I lags replaces
+ * the low-rank steps. */
+fcc_status fcc_tdoa_from_spectra(fcc_plan plan, const void* d_basis,
+                                 const void* d_spec, int64_t num_frames,
+                                 int32_t* d_tdoa, hipStream_t stream);
+
+/* Same as fcc_tdoa_from_spectra, but writes the correlation itself:
+ * d_y [T][P][I] FP32, lag index i <-> tau_i = i / r - tau_max.  For parity
+ * checks and inspection. */
+fcc_status fcc_correlation(fcc_plan plan, const void* d_basis,
+                           const void* d_spec, int64_t num_frames, float* d_y,
+                           hipStream_t stream);
+
+/* Host copies of the FP64 basis (Sec. 4), for inspection and tests.  Any
+ * pointer may be NULL.  Order of components: symmetric, antisymmetric,
+ * symmetric, ... (eq. 6).
+ *   sigma [D], is_sym [D], p_hat [D][N/4+1] (eq. 7 rows, sigma included),
+ *   dc, ds [I][D] real and imaginary parts of the dictionary U. */
+fcc_status fcc_basis_export(fcc_plan plan, double* sigma, int32_t* is_sym,
+                            double* p_hat, double* dc, double* ds);
+
+const char* fcc_status_string(fcc_status status);
+const char* fcc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FCC_H_ */

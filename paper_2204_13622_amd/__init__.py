@@ -1,0 +1,226 @@
+"""MI355X (gfx950) Fast Cross-Correlation TDoA: Python binding of libfcc.so.
+
+The binding only marshals arguments: every step of the path runs in the HIP
+kernels of libfcc.so.  PyTorch provides device memory and the current stream.
+
+    plan = Plan(mic_xyz, fs=16000, frame_size=512, hop=128, rank=6)
+    tdoa = plan.tdoa(x)            # x: float32 [M, L] on a HIP device -> int32 [T, P]
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import FccError, PRECISIONS, METHODS
+
+__all__ = ["Plan", "FccError", "PRECISIONS", "METHODS", "library_path"]
+
+
+def library_path() -> str:
+    return _lib.LIB_PATH
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(device) -> ctypes.c_void_p:
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """One array geometry: FP64 basis built on the host, tables on each device.
+
+    Arguments follow the problem statement of the paper (Sec. 2): microphone
+    positions (metres), sample rate, speed of sound, frame size N, hop, lag
+    range tau_max (0: from the geometry) and rank D (0: full rank).
+    """
+
+    def __init__(self, mic_xyz, fs: float, c: float = 343.0, frame_size: int = 512,
+                 hop: int = 128, tau_max: int = 0, rank: int = 0, interp: int = 1,
+                 alpha: float = 1.0, precision: str = "fp32", method: str = "fcc"):
+        lib = _lib.load()
+        self._lib = lib
+        xyz = np.ascontiguousarray(np.asarray(mic_xyz, dtype=np.float64).reshape(-1, 3))
+        self.mic_xyz = xyz
+        self.precision = precision
+        self.method = method
+        cfg = _lib.FccConfig()
+        cfg.num_mics = xyz.shape[0]
+        cfg.mic_xyz = xyz.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        cfg.fs, cfg.c = float(fs), float(c)
+        cfg.frame_size, cfg.hop = int(frame_size), int(hop)
+        cfg.tau_max, cfg.rank, cfg.interp = int(tau_max), int(rank), int(interp)
+        cfg.alpha = float(alpha)
+        if precision not in PRECISIONS or method not in METHODS:
+            raise ValueError(f"precision in {sorted(PRECISIONS)}, method in {sorted(METHODS)}")
+        cfg.precision = PRECISIONS[precision]
+        cfg.method = METHODS[method]
+        handle = ctypes.c_void_p()
+        _lib.check(lib.fcc_plan_create(ctypes.byref(cfg), ctypes.byref(handle)))
+        self._h = handle
+        info = _lib.FccPlanInfo()
+        _lib.check(lib.fcc_plan_query(self._h, ctypes.byref(info)))
+        self.info = info
+        self._basis = {}
+
+    # ---- geometry / shapes -------------------------------------------------
+    @property
+    def M(self) -> int: return self.info.num_mics
+    @property
+    def P(self) -> int: return self.info.num_pairs
+    @property
+    def N(self) -> int: return self.info.frame_size
+    @property
+    def hop(self) -> int: return self.info.hop
+    @property
+    def F(self) -> int: return self.info.num_bins
+    @property
+    def tau_max(self) -> int: return self.info.tau_max
+    @property
+    def I(self) -> int: return self.info.num_lags
+    @property
+    def rank(self) -> int: return self.info.rank
+
+    def pairs(self):
+        return [(i, j) for i in range(self.M) for j in range(i + 1, self.M)]
+
+    def num_frames(self, num_samples: int) -> int:
+        out = ctypes.c_int64()
+        _lib.check(self._lib.fcc_num_frames(self._h, int(num_samples), ctypes.byref(out)))
+        return out.value
+
+    def workspace_bytes(self, num_frames: int) -> int:
+        out = ctypes.c_size_t()
+        _lib.check(self._lib.fcc_workspace_bytes(self._h, int(num_frames), ctypes.byref(out)))
+        return out.value
+
+    def spectrum_dtype(self):
+        torch = _torch()
+        return {"fp32": torch.float32, "bf16": torch.bfloat16, "fp16": torch.float16,
+                "fp8": torch.float8_e4m3fn, "fp8_e4m3": torch.float8_e4m3fn}[self.precision]
+
+    # ---- device tables -------------------------------------------------------
+    def basis_tensor(self, device=None):
+        """The plan's packed tables on `device` (uploaded once per device)."""
+        torch = _torch()
+        dev = torch.device(device if device is not None else "cuda")
+        if dev.index is None:
+            dev = torch.device("cuda", torch.cuda.current_device())
+        buf = self._basis.get(dev.index)
+        if buf is None:
+            nbytes = self.info.basis_bytes
+            raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+            off = (-raw.data_ptr()) % 256
+            buf = raw[off:off + nbytes]
+            with torch.cuda.device(dev):
+                _lib.check(self._lib.fcc_plan_upload(self._h, _ptr(buf), _stream_handle(dev)))
+            self._basis[dev.index] = buf
+        return buf
+
+    # ---- hot path ------------------------------------------------------------
+    def _check_audio(self, x):
+        torch = _torch()
+        if not isinstance(x, torch.Tensor) or x.device.type != "cuda":
+            raise TypeError("x must be a torch tensor on a HIP device")
+        if x.dtype != torch.float32 or x.dim() != 2 or x.shape[0] != self.M:
+            raise ValueError(f"x must be float32 [M={self.M}, L]")
+        if x.stride(1) != 1:
+            raise ValueError("x rows must be contiguous")
+        return x.shape[1], x.stride(0)
+
+    def spectra(self, x, out=None):
+        """Whitened spectra [T, M, F, 2] (re, im) in the plan's storage type."""
+        torch = _torch()
+        L, ld = self._check_audio(x)
+        T = self.num_frames(L)
+        if out is None:
+            out = torch.empty((T, self.M, self.F, 2), dtype=self.spectrum_dtype(), device=x.device)
+        basis = self.basis_tensor(x.device)
+        with torch.cuda.device(x.device):
+            _lib.check(self._lib.fcc_spectra(self._h, _ptr(basis), _ptr(x), L, ld, _ptr(out),
+                                             _stream_handle(x.device)))
+        return out
+
+    def tdoa(self, x, out=None, workspace=None):
+        """Integer TDoA [T, P] (int32, samples) from audio x [M, L] float32."""
+        torch = _torch()
+        L, ld = self._check_audio(x)
+        T = self.num_frames(L)
+        if out is None:
+            out = torch.empty((T, self.P), dtype=torch.int32, device=x.device)
+        if workspace is None:
+            workspace = torch.empty(max(self.workspace_bytes(T), 256), dtype=torch.uint8,
+                                    device=x.device)
+        basis = self.basis_tensor(x.device)
+        with torch.cuda.device(x.device):
+            _lib.check(self._lib.fcc_tdoa(self._h, _ptr(basis), _ptr(x), L, ld, _ptr(out),
+                                          _ptr(workspace), _stream_handle(x.device)))
+        return out
+
+    def _check_spec(self, spec):
+        torch = _torch()
+        if not isinstance(spec, torch.Tensor) or spec.device.type != "cuda":
+            raise TypeError("spectra must be a torch tensor on a HIP device")
+        if spec.dtype != self.spectrum_dtype() or not spec.is_contiguous():
+            raise ValueError("spectra must be contiguous in the plan's storage type")
+        if spec.dim() != 4 or tuple(spec.shape[1:]) != (self.M, self.F, 2):
+            raise ValueError(f"spectra must be [T, {self.M}, {self.F}, 2]")
+        return spec.shape[0]
+
+    def tdoa_from_spectra(self, spec, out=None):
+        torch = _torch()
+        T = self._check_spec(spec)
+        if out is None:
+            out = torch.empty((T, self.P), dtype=torch.int32, device=spec.device)
+        basis = self.basis_tensor(spec.device)
+        with torch.cuda.device(spec.device):
+            _lib.check(self._lib.fcc_tdoa_from_spectra(self._h, _ptr(basis), _ptr(spec), T,
+                                                       _ptr(out), _stream_handle(spec.device)))
+        return out
+
+    def correlation(self, spec, out=None):
+        """y [T, P, I] float32 at lags tau_i = i - tau_max."""
+        torch = _torch()
+        T = self._check_spec(spec)
+        if out is None:
+            out = torch.empty((T, self.P, self.I), dtype=torch.float32, device=spec.device)
+        basis = self.basis_tensor(spec.device)
+        with torch.cuda.device(spec.device):
+            _lib.check(self._lib.fcc_correlation(self._h, _ptr(basis), _ptr(spec), T, _ptr(out),
+                                                 _stream_handle(spec.device)))
+        return out
+
+    # ---- host-side inspection ------------------------------------------------
+    def basis_export(self) -> dict:
+        D, I, Bs = self.rank, self.I, self.N // 4 + 1
+        sigma = np.zeros(D)
+        is_sym = np.zeros(D, dtype=np.int32)
+        p_hat = np.zeros((D, Bs))
+        dc = np.zeros((I, D))
+        ds = np.zeros((I, D))
+        dp = ctypes.POINTER(ctypes.c_double)
+        _lib.check(self._lib.fcc_basis_export(
+            self._h, sigma.ctypes.data_as(dp), is_sym.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+            p_hat.ctypes.data_as(dp), dc.ctypes.data_as(dp), ds.ctypes.data_as(dp)))
+        return {"sigma": sigma, "is_sym": is_sym.astype(bool), "p_hat": p_hat, "Dc": dc, "Ds": ds}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.fcc_plan_destroy(self._h)
+            self._h = None
+        self._basis = {}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,264 @@
+// C ABI of the FCC library: plan lifecycle, argument checks and dispatch.
+// The contract of every entry point is documented in include/fcc.h.
+#include <hip/hip_runtime_api.h>
+
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "fcc.h"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+struct fcc_plan_s {
+  fcc::Plan p;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+fcc_status set_error(fcc_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+fcc_status hip_status(hipError_t e, const char* what) {
+  if (e == hipSuccess) return FCC_OK;
+  return set_error(FCC_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+int64_t frames_of(const fcc::Plan& p, int64_t L) {
+  if (L < p.N) return 0;
+  return (L - p.N) / p.hop + 1;
+}
+
+const unsigned char* image_ptr(const void* d_basis, size_t off) {
+  return static_cast<const unsigned char*>(d_basis) + off;
+}
+
+fcc_status check_basis(const void* d_basis) {
+  if (!d_basis) return set_error(FCC_ERR_INVALID_ARG, "d_basis is NULL");
+  if (!aligned(d_basis, 256)) return set_error(FCC_ERR_INVALID_ARG, "d_basis must be 256-byte aligned");
+  return FCC_OK;
+}
+
+fcc_status check_spec(const fcc::Plan& p, const void* d_spec) {
+  if (!d_spec) return set_error(FCC_ERR_INVALID_ARG, "spectrum pointer is NULL");
+  if (!aligned(d_spec, size_t(p.spec_elem))) return set_error(FCC_ERR_INVALID_ARG, "spectrum pointer misaligned");
+  return FCC_OK;
+}
+
+fcc::PairArgs pair_args(const fcc::Plan& p, const void* d_basis, const void* d_spec, int64_t T,
+                        hipStream_t stream) {
+  fcc::PairArgs a{};
+  a.spec = d_spec;
+  a.T = T;
+  a.M = p.M;
+  a.P = p.P;
+  a.N = p.N;
+  a.I = p.I;
+  a.D = p.D;
+  a.tau_max = p.tau_max;
+  a.precision = p.precision;
+  a.method = p.method;
+  a.pairs = reinterpret_cast<const uint8_t*>(image_ptr(d_basis, p.layout.pairs));
+  a.basis32 = reinterpret_cast<const float*>(image_ptr(d_basis, p.layout.basis32));
+  a.dict = reinterpret_cast<const float*>(image_ptr(d_basis, p.layout.dict));
+  a.lagw = reinterpret_cast<const float2*>(image_ptr(d_basis, p.layout.lagw));
+  a.stream = stream;
+  return a;
+}
+
+fcc_status run_spectra(const fcc::Plan& p, const void* d_basis, const float* d_x, int64_t L,
+                       int64_t ld, void* d_spec, hipStream_t stream) {
+  fcc::StftArgs a{};
+  a.x = d_x;
+  a.ld = ld;
+  a.T = frames_of(p, L);
+  a.M = p.M;
+  a.N = p.N;
+  a.hop = p.hop;
+  a.precision = p.precision;
+  a.window = reinterpret_cast<const float*>(image_ptr(d_basis, p.layout.window));
+  a.twiddle = reinterpret_cast<const float2*>(image_ptr(d_basis, p.layout.twiddle));
+  a.out = d_spec;
+  a.stream = stream;
+  return hip_status(fcc::launch_stft_phat(a), "stft_phat launch");
+}
+
+fcc_status check_audio(const fcc::Plan& p, const float* d_x, int64_t L, int64_t ld) {
+  if (L < 0) return set_error(FCC_ERR_INVALID_ARG, "num_samples must be >= 0");
+  if (ld < L || ld <= 0) return set_error(FCC_ERR_INVALID_ARG, "ld must be >= num_samples and > 0");
+  if (frames_of(p, L) > 0 && !d_x) return set_error(FCC_ERR_INVALID_ARG, "d_x is NULL");
+  if (!aligned(d_x, 4)) return set_error(FCC_ERR_INVALID_ARG, "d_x misaligned");
+  if (frames_of(p, L) * int64_t(p.M) > int64_t(INT32_MAX))
+    return set_error(FCC_ERR_UNSUPPORTED, "too many frames for one call");
+  return FCC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fcc_status fcc_plan_create(const fcc_config* config, fcc_plan* out) {
+  if (!config || !out) return set_error(FCC_ERR_INVALID_ARG, "NULL argument");
+  *out = nullptr;
+  fcc_plan_s* h = new (std::nothrow) fcc_plan_s;
+  if (!h) return set_error(FCC_ERR_INTERNAL, "out of host memory");
+  std::string err;
+  fcc_status st;
+  try {
+    st = fcc::build_plan(*config, h->p, err);
+  } catch (...) {
+    st = FCC_ERR_INTERNAL;
+    err = "exception while building the plan";
+  }
+  if (st != FCC_OK) {
+    delete h;
+    return set_error(st, err);
+  }
+  *out = h;
+  return FCC_OK;
+}
+
+void fcc_plan_destroy(fcc_plan plan) { delete plan; }
+
+fcc_status fcc_plan_query(fcc_plan plan, fcc_plan_info* info) {
+  if (!plan || !info) return set_error(FCC_ERR_INVALID_ARG, "NULL argument");
+  const fcc::Plan& p = plan->p;
+  info->num_mics = p.M;
+  info->num_pairs = p.P;
+  info->frame_size = p.N;
+  info->hop = p.hop;
+  info->num_bins = p.F;
+  info->tau_max = p.tau_max;
+  info->num_lags = p.I;
+  info->rank = p.D;
+  info->rank_sym = p.Ds;
+  info->rank_anti = p.Da;
+  info->precision = p.precision;
+  info->method = p.method;
+  info->basis_bytes = p.layout.total;
+  info->spectrum_bytes_per_frame = size_t(p.M) * p.F * p.spec_elem;
+  info->spectrum_elem_bytes = p.spec_elem;
+  return FCC_OK;
+}
+
+fcc_status fcc_plan_upload(fcc_plan plan, void* d_basis, hipStream_t stream) {
+  if (!plan) return set_error(FCC_ERR_INVALID_ARG, "NULL plan");
+  fcc_status st = check_basis(d_basis);
+  if (st != FCC_OK) return st;
+  const fcc::Plan& p = plan->p;
+  return hip_status(hipMemcpyAsync(d_basis, p.image.data(), p.image.size(), hipMemcpyHostToDevice, stream),
+                    "plan upload");
+}
+
+fcc_status fcc_num_frames(fcc_plan plan, int64_t num_samples, int64_t* num_frames) {
+  if (!plan || !num_frames) return set_error(FCC_ERR_INVALID_ARG, "NULL argument");
+  if (num_samples < 0) return set_error(FCC_ERR_INVALID_ARG, "num_samples must be >= 0");
+  *num_frames = frames_of(plan->p, num_samples);
+  return FCC_OK;
+}
+
+fcc_status fcc_workspace_bytes(fcc_plan plan, int64_t num_frames, size_t* bytes) {
+  if (!plan || !bytes) return set_error(FCC_ERR_INVALID_ARG, "NULL argument");
+  if (num_frames < 0) return set_error(FCC_ERR_INVALID_ARG, "num_frames must be >= 0");
+  const fcc::Plan& p = plan->p;
+  const size_t b = size_t(num_frames) * p.M * p.F * p.spec_elem;
+  *bytes = (b + 255) & ~size_t(255);
+  return FCC_OK;
+}
+
+fcc_status fcc_spectra(fcc_plan plan, const void* d_basis, const float* d_x, int64_t num_samples,
+                       int64_t ld, void* d_spec, hipStream_t stream) {
+  if (!plan) return set_error(FCC_ERR_INVALID_ARG, "NULL plan");
+  const fcc::Plan& p = plan->p;
+  fcc_status st = check_basis(d_basis);
+  if (st == FCC_OK) st = check_audio(p, d_x, num_samples, ld);
+  if (st != FCC_OK) return st;
+  if (frames_of(p, num_samples) == 0) return FCC_OK;
+  if ((st = check_spec(p, d_spec)) != FCC_OK) return st;
+  return run_spectra(p, d_basis, d_x, num_samples, ld, d_spec, stream);
+}
+
+static fcc_status pair_stage(const fcc::Plan& p, const void* d_basis, const void* d_spec, int64_t T,
+                             int32_t* d_tdoa, float* d_y, hipStream_t stream) {
+  if (T < 0) return set_error(FCC_ERR_INVALID_ARG, "num_frames must be >= 0");
+  fcc_status st = check_basis(d_basis);
+  if (st != FCC_OK) return st;
+  if (T == 0) return FCC_OK;
+  if ((st = check_spec(p, d_spec)) != FCC_OK) return st;
+  if (!d_tdoa && !d_y) return set_error(FCC_ERR_INVALID_ARG, "output pointer is NULL");
+  if (d_tdoa && !aligned(d_tdoa, 4)) return set_error(FCC_ERR_INVALID_ARG, "d_tdoa misaligned");
+  if (d_y && !aligned(d_y, 4)) return set_error(FCC_ERR_INVALID_ARG, "d_y misaligned");
+  if (T > int64_t(INT32_MAX)) return set_error(FCC_ERR_UNSUPPORTED, "too many frames for one call");
+  fcc::PairArgs a = pair_args(p, d_basis, d_spec, T, stream);
+  a.tdoa = d_tdoa;
+  a.y = d_y;
+  const hipError_t e = fcc::launch_pair_valu(a);
+  if (e == hipErrorInvalidValue)
+    return set_error(FCC_ERR_UNSUPPORTED, "shape outside the pair kernel's limits");
+  return hip_status(e, "pair kernel launch");
+}
+
+fcc_status fcc_tdoa_from_spectra(fcc_plan plan, const void* d_basis, const void* d_spec,
+                                 int64_t num_frames, int32_t* d_tdoa, hipStream_t stream) {
+  if (!plan) return set_error(FCC_ERR_INVALID_ARG, "NULL plan");
+  if (num_frames > 0 && !d_tdoa) return set_error(FCC_ERR_INVALID_ARG, "d_tdoa is NULL");
+  return pair_stage(plan->p, d_basis, d_spec, num_frames, d_tdoa, nullptr, stream);
+}
+
+fcc_status fcc_correlation(fcc_plan plan, const void* d_basis, const void* d_spec, int64_t num_frames,
+                           float* d_y, hipStream_t stream) {
+  if (!plan) return set_error(FCC_ERR_INVALID_ARG, "NULL plan");
+  if (num_frames > 0 && !d_y) return set_error(FCC_ERR_INVALID_ARG, "d_y is NULL");
+  return pair_stage(plan->p, d_basis, d_spec, num_frames, nullptr, d_y, stream);
+}
+
+fcc_status fcc_tdoa(fcc_plan plan, const void* d_basis, const float* d_x, int64_t num_samples, int64_t ld,
+                    int32_t* d_tdoa, void* d_workspace, hipStream_t stream) {
+  if (!plan) return set_error(FCC_ERR_INVALID_ARG, "NULL plan");
+  const fcc::Plan& p = plan->p;
+  fcc_status st = check_basis(d_basis);
+  if (st == FCC_OK) st = check_audio(p, d_x, num_samples, ld);
+  if (st != FCC_OK) return st;
+  const int64_t T = frames_of(p, num_samples);
+  if (T == 0) return FCC_OK;
+  if (!d_tdoa) return set_error(FCC_ERR_INVALID_ARG, "d_tdoa is NULL");
+  if (!d_workspace) return set_error(FCC_ERR_INVALID_ARG, "d_workspace is NULL");
+  if ((st = check_spec(p, d_workspace)) != FCC_OK) return st;
+  if ((st = run_spectra(p, d_basis, d_x, num_samples, ld, d_workspace, stream)) != FCC_OK) return st;
+  return pair_stage(p, d_basis, d_workspace, T, d_tdoa, nullptr, stream);
+}
+
+fcc_status fcc_basis_export(fcc_plan plan, double* sigma, int32_t* is_sym, double* p_hat, double* dc,
+                            double* ds) {
+  if (!plan) return set_error(FCC_ERR_INVALID_ARG, "NULL plan");
+  const fcc::Plan& p = plan->p;
+  if (sigma) std::memcpy(sigma, p.sigma.data(), sizeof(double) * p.sigma.size());
+  if (is_sym) std::memcpy(is_sym, p.is_sym.data(), sizeof(int32_t) * p.is_sym.size());
+  if (p_hat) std::memcpy(p_hat, p.p_hat.data(), sizeof(double) * p.p_hat.size());
+  if (dc) std::memcpy(dc, p.dc.data(), sizeof(double) * p.dc.size());
+  if (ds) std::memcpy(ds, p.ds.data(), sizeof(double) * p.ds.size());
+  return FCC_OK;
+}
+
+const char* fcc_status_string(fcc_status status) {
+  switch (status) {
+    case FCC_OK: return "FCC_OK";
+    case FCC_ERR_INVALID_ARG: return "FCC_ERR_INVALID_ARG";
+    case FCC_ERR_UNSUPPORTED: return "FCC_ERR_UNSUPPORTED";
+    case FCC_ERR_BASIS_AMBIGUOUS: return "FCC_ERR_BASIS_AMBIGUOUS";
+    case FCC_ERR_HIP: return "FCC_ERR_HIP";
+    case FCC_ERR_INTERNAL: return "FCC_ERR_INTERNAL";
+  }
+  return "unknown fcc_status";
+}
+
+const char* fcc_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

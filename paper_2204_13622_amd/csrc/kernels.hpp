@@ -1,0 +1,41 @@
+// Launch interfaces of the device kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fcc.h"
+
+namespace fcc {
+
+struct StftArgs {
+  const float* x;            // [M][ld] audio
+  int64_t ld;
+  int64_t T;                 // frames
+  int M, N, hop;
+  fcc_precision precision;
+  const float* window;       // [N]
+  const float2* twiddle;     // [N/2 + 1]
+  void* out;                 // [T][M][N/2 + 1] complex, storage format
+  hipStream_t stream;
+};
+
+struct PairArgs {
+  const void* spec;          // [T][M][F] complex, storage format
+  int64_t T;
+  int M, P, N, I, D, tau_max;
+  fcc_precision precision;
+  fcc_method method;
+  const uint8_t* pairs;      // [P][2]
+  const float* basis32;      // [D][N/4 + 1]
+  const float* dict;         // [I][2D]   (2 Dc, -2 Ds)
+  const float2* lagw;        // [I][F]    exp(j 2 pi f tau_i / N)
+  int32_t* tdoa;             // [T][P] or null
+  float* y;                  // [T][P][I] or null
+  hipStream_t stream;
+};
+
+hipError_t launch_stft_phat(const StftArgs& a);
+hipError_t launch_pair_valu(const PairArgs& a);
+
+}  // namespace fcc

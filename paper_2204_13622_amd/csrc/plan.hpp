@@ -1,0 +1,58 @@
+// Host-side plan of the FCC library: configuration, FP64 basis and the packed
+// device image.  Pure C++17; no HIP calls.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "fcc.h"
+
+namespace fcc {
+
+// Offsets (bytes) of the tables inside the device image; each is 256-aligned.
+struct ImageLayout {
+  size_t window = 0;      // float [N]           periodic Hann window
+  size_t twiddle = 0;     // float2 [N/2 + 1]    exp(-j 2 pi f / N)
+  size_t pairs = 0;       // uint8 [P][2]        (i, j), lexicographic
+  size_t basis32 = 0;     // float [D][Bs]       p_hat rows, Bs = N/4 + 1
+  size_t dict = 0;        // float [I][2D]       (2 Dc, -2 Ds) interleaved per k
+  size_t basis16 = 0;     // uint16 [Dpad][Kpad] p_hat in the plan's 16-bit type
+  size_t basis8 = 0;      // uint8 [Dpad][Kpad]  p_hat in e4m3
+  size_t lagw = 0;        // float2 [I][F]       exp(j 2 pi f tau_i / N) (GCC)
+  size_t total = 0;
+};
+
+struct Plan {
+  // configuration
+  int M = 0, P = 0, N = 0, hop = 0, F = 0, m = 0;
+  int tau_max = 0, r = 1, I = 0, D = 0, Ds = 0, Da = 0;
+  double fs = 0, c = 0;
+  float alpha = 1.0f;
+  fcc_precision precision = FCC_FP32;
+  fcc_method method = FCC_METHOD_FCC;
+  std::vector<double> xyz;          // [M][3]
+
+  // FP64 basis in component order S, A, S, A, ... (eq. 6)
+  std::vector<double> sigma;        // [D]
+  std::vector<int32_t> is_sym;      // [D]
+  std::vector<double> p_hat;        // [D][m + 1]
+  std::vector<double> dc, ds;       // [I][D]
+
+  // packed device image
+  ImageLayout layout;
+  std::vector<unsigned char> image;
+  int Kpad = 0, Dpad = 0;           // padded MFMA operand shapes
+  int spec_elem = 8;                // bytes per complex spectrum element
+};
+
+// Builds a plan; on error returns the status and fills `err`.
+fcc_status build_plan(const fcc_config& cfg, Plan& plan, std::string& err);
+
+// One-sided (Hestenes) Jacobi SVD of B given as q columns of length n
+// (column-major, n >= q).  On return the columns of B are B0 J with mutually
+// orthogonal columns and J (q x q, column-major) is orthogonal.
+void jacobi_one_sided(std::vector<double>& B, int n, int q, std::vector<double>& J);
+
+}  // namespace fcc

@@ -1,0 +1,127 @@
+"""C-ABI library on the host (no GPU calls): exports, configuration checks,
+and the FP64 host basis against the oracle's."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle.fcc_oracle as O
+from gen import circular_array, square_array
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def fcc():
+    import paper_2204_13622_amd as fcc
+    fcc._lib.load()
+    return fcc
+
+
+def _declared_functions():
+    with open(os.path.join(ROOT, "include", "fcc.h")) as fh:
+        src = fh.read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fcc_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(fcc):
+    lib = ctypes.CDLL(fcc.library_path())
+    declared = _declared_functions()
+    assert len(declared) >= 13
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(declared) == set(fcc._lib.EXPORTS)
+
+
+def test_status_strings(fcc):
+    lib = fcc._lib.load()
+    for code, name in fcc._lib.STATUS_NAMES.items():
+        assert lib.fcc_status_string(code).decode() == name
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(mic_xyz=np.zeros((1, 3))), "FCC_ERR_INVALID_ARG"),
+    (dict(frame_size=500), "FCC_ERR_INVALID_ARG"),
+    (dict(frame_size=8), "FCC_ERR_INVALID_ARG"),
+    (dict(hop=0), "FCC_ERR_INVALID_ARG"),
+    (dict(fs=-1.0), "FCC_ERR_INVALID_ARG"),
+    (dict(c=0.0), "FCC_ERR_INVALID_ARG"),
+    (dict(rank=10), "FCC_ERR_INVALID_ARG"),          # I = 9 for the 5 cm square
+    (dict(tau_max=128), "FCC_ERR_INVALID_ARG"),      # must stay below N/4
+    (dict(interp=2), "FCC_ERR_UNSUPPORTED"),
+    (dict(alpha=0.1), "FCC_ERR_UNSUPPORTED"),
+    (dict(mic_xyz=circular_array(33, 0.05)), "FCC_ERR_UNSUPPORTED"),
+])
+def test_invalid_configs(fcc, kw, status):
+    args = dict(mic_xyz=square_array(0.05), fs=16000.0, frame_size=512, hop=128)
+    args.update(kw)
+    with pytest.raises(fcc.FccError) as ei:
+        fcc.Plan(**args)
+    assert ei.value.name == status
+
+
+def test_ambiguous_rank_refused(fcc):
+    with pytest.raises(fcc.FccError) as ei:
+        fcc.Plan(circular_array(16, 0.05), 48000.0, frame_size=1024, hop=256, rank=3)
+    assert ei.value.name == "FCC_ERR_BASIS_AMBIGUOUS"
+    with pytest.raises(O.BasisAmbiguous):
+        O.fcc_basis(1024, 14, 3)
+
+
+def test_plan_query(fcc):
+    p = fcc.Plan(circular_array(16, 0.05), 16000.0, frame_size=512, hop=128, rank=6)
+    assert (p.M, p.P, p.N, p.F, p.tau_max, p.I, p.rank) == (16, 120, 512, 257, 5, 11, 6)
+    assert (p.info.rank_sym, p.info.rank_anti) == (3, 3)
+    assert p.num_frames(960000) == 7497 and p.num_frames(511) == 0 and p.num_frames(512) == 1
+    assert p.info.spectrum_bytes_per_frame == 16 * 257 * 8
+    assert p.workspace_bytes(7497) % 256 == 0
+    assert fcc.Plan(square_array(0.05), 16000.0, precision="bf16").info.spectrum_elem_bytes == 4
+    assert fcc.Plan(square_array(0.05), 16000.0, precision="fp8").info.spectrum_elem_bytes == 2
+    g = fcc.Plan(square_array(0.05), 16000.0, method="gcc")
+    assert g.rank == g.I == 9
+
+
+def _operator(e, N):
+    """Rank-D frequency-to-lag operator U S V^T rebuilt from exported tables."""
+    m, F = N // 4, N // 2 + 1
+    D = len(e["sigma"])
+    V = np.zeros((D, F))
+    f = np.arange(m)
+    for k in range(D):
+        v = e["p_hat"][k] / e["sigma"][k]
+        V[k, f] = v[:m]
+        V[k, N // 2 - f] = v[:m] if e["is_sym"][k] else -v[:m]
+        V[k, m] = v[m]
+    return (e["Dc"] + 1j * e["Ds"]) @ (e["sigma"][:, None] * V)
+
+
+@pytest.mark.parametrize("xyz,fs,N,D", [
+    (square_array(0.05), 16000.0, 512, 9),
+    (circular_array(16, 0.05), 16000.0, 512, 6),
+    (circular_array(16, 0.05), 16000.0, 512, 11),
+    (circular_array(16, 0.05), 48000.0, 1024, 15),
+    (circular_array(16, 0.05), 48000.0, 1024, 29),
+    (circular_array(8, 0.04), 16000.0, 512, 5),
+    (np.array([[0, 0, 0], [0.15, 0, 0]]), 16000.0, 512, 8),
+])
+def test_host_basis_matches_oracle(fcc, xyz, fs, N, D):
+    p = fcc.Plan(xyz, fs, frame_size=N, hop=N // 4, rank=D)
+    assert p.tau_max == O.tau_max_from_geometry(xyz, fs, 343.0)
+    e = p.basis_export()
+    B = O.fcc_basis(N, p.tau_max, D)
+    assert list(e["is_sym"]) == list(B.is_sym)
+    assert np.abs(e["sigma"] - B.sigma).max() < 1e-12 * B.sigma[0]
+    # the rank-D subspace is unique (refused otherwise); vectors inside a
+    # cluster of equal singular values are not, so compare the operator
+    Ob = (B.Dc + 1j * B.Ds) @ (B.sigma[:, None] * B.v_full)
+    assert np.abs(_operator(e, N) - Ob).max() < 1e-12 * B.sigma[0]
+    # exact structure of the host tables
+    m = N // 4
+    for k in range(D):
+        if not e["is_sym"][k]:
+            assert e["p_hat"][k, m] == 0.0
+    assert np.array_equal(e["Dc"], e["Dc"][::-1])
+    assert np.array_equal(e["Ds"], -e["Ds"][::-1])
