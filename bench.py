@@ -57,7 +57,7 @@ def time_loop(torch, fn, steps):
 def kernel_bytes(plan, L, T):
     """Algorithmic HBM bytes of one launch of each kernel."""
     esz = plan.info.spectrum_elem_bytes
-    spec = T * plan.M * plan.F * esz
+    spec = T * plan.M * (plan.N // 2) * esz
     return {
         "stft_phat": plan.M * L * 4 + spec,              # audio once + spectra written
         "pair": spec + T * plan.P * 4,                   # spectra once + TDoA written
@@ -143,8 +143,8 @@ def main():
     value = T * P / (ms * 1e-3)
 
     # per-kernel averages over their own timed loops (same stream)
-    spec_view = ws[:T * plan.M * plan.F * plan.info.spectrum_elem_bytes].view(
-        plan.spectrum_dtype()).view(T, plan.M, plan.F, 2)
+    spec_view = ws[:T * plan.info.spectrum_bytes_per_frame].view(
+        plan.spectrum_dtype()).view(T, plan.M, plan.N // 2, 2)
     ms_stft = time_loop(torch, lambda: plan.spectra(x, out=spec_view), args.steps)
     ms_pair = time_loop(torch, lambda: plan.tdoa_from_spectra(spec_view, out=out), args.steps)
     kb = kernel_bytes(plan, rec.L, T)

@@ -102,7 +102,7 @@ typedef struct {
   int32_t precision;              /* fcc_precision                            */
   int32_t method;                 /* fcc_method                               */
   size_t basis_bytes;             /* size of the device plan buffer           */
-  size_t spectrum_bytes_per_frame;/* M * F * (complex element size)           */
+  size_t spectrum_bytes_per_frame;/* M * (N/2) * (complex element size)       */
   int32_t spectrum_elem_bytes;    /* 8 (FP32), 4 (BF16/FP16), 2 (FP8)         */
 } fcc_plan_info;
 
@@ -139,7 +139,9 @@ fcc_status fcc_workspace_bytes(fcc_plan plan, int64_t num_frames, size_t* bytes)
  * alpha = 1, R_ij / |R_ij| = e_i e_j^* with e = X / |X|).  A bin whose squared
  * magnitude is below FLT_MIN becomes 0.
  *   d_x    [M][ld] FP32 audio, row m at d_x + m * ld, L samples used, ld >= L.
- *   d_spec [T][M][F] complex, interleaved (re, im), in the plan's precision.
+ *   d_spec [T][M][N/2] complex slots, interleaved (re, im), in the plan's
+ *          precision ("packed real spectrum"): slot 0 holds (e(0), e(N/2)),
+ *          the two real bins; slot f holds e(f) for 0 < f < N/2.
  * T = fcc_num_frames(L); T = 0 enqueues nothing. */
 fcc_status fcc_spectra(fcc_plan plan, const void* d_basis, const float* d_x,
                        int64_t num_samples, int64_t ld, void* d_spec,

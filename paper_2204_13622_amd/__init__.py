@@ -90,6 +90,24 @@ class Plan:
     @property
     def rank(self) -> int: return self.info.rank
 
+    @staticmethod
+    def pack_spectrum(e):
+        """[..., N/2 + 1] complex bins -> [..., N/2, 2] packed real layout."""
+        e = np.asarray(e)
+        out = np.stack([e[..., :-1].real, e[..., :-1].imag], axis=-1)
+        out[..., 0, 1] = e[..., -1].real
+        return out
+
+    @staticmethod
+    def unpack_spectrum(a):
+        """[..., N/2, 2] packed real layout -> [..., N/2 + 1] complex bins."""
+        a = np.asarray(a, dtype=np.float64)
+        e = np.empty(a.shape[:-2] + (a.shape[-2] + 1,), dtype=np.complex128)
+        e[..., :-1] = a[..., 0] + 1j * a[..., 1]
+        e[..., 0] = a[..., 0, 0]
+        e[..., -1] = a[..., 0, 1]
+        return e
+
     def pairs(self):
         return [(i, j) for i in range(self.M) for j in range(i + 1, self.M)]
 
@@ -138,12 +156,13 @@ class Plan:
         return x.shape[1], x.stride(0)
 
     def spectra(self, x, out=None):
-        """Whitened spectra [T, M, F, 2] (re, im) in the plan's storage type."""
+        """Whitened spectra [T, M, N/2, 2] (re, im) in the plan's storage type,
+        packed real layout: slot 0 holds (e(0), e(N/2)), slot f holds e(f)."""
         torch = _torch()
         L, ld = self._check_audio(x)
         T = self.num_frames(L)
         if out is None:
-            out = torch.empty((T, self.M, self.F, 2), dtype=self.spectrum_dtype(), device=x.device)
+            out = torch.empty((T, self.M, self.N // 2, 2), dtype=self.spectrum_dtype(), device=x.device)
         basis = self.basis_tensor(x.device)
         with torch.cuda.device(x.device):
             _lib.check(self._lib.fcc_spectra(self._h, _ptr(basis), _ptr(x), L, ld, _ptr(out),
@@ -172,8 +191,8 @@ class Plan:
             raise TypeError("spectra must be a torch tensor on a HIP device")
         if spec.dtype != self.spectrum_dtype() or not spec.is_contiguous():
             raise ValueError("spectra must be contiguous in the plan's storage type")
-        if spec.dim() != 4 or tuple(spec.shape[1:]) != (self.M, self.F, 2):
-            raise ValueError(f"spectra must be [T, {self.M}, {self.F}, 2]")
+        if spec.dim() != 4 or tuple(spec.shape[1:]) != (self.M, self.N // 2, 2):
+            raise ValueError(f"spectra must be [T, {self.M}, {self.N // 2}, 2]")
         return spec.shape[0]
 
     def tdoa_from_spectra(self, spec, out=None):

@@ -69,6 +69,10 @@ fcc::PairArgs pair_args(const fcc::Plan& p, const void* d_basis, const void* d_s
   a.basis32 = reinterpret_cast<const float*>(image_ptr(d_basis, p.layout.basis32));
   a.dict = reinterpret_cast<const float*>(image_ptr(d_basis, p.layout.dict));
   a.lagw = reinterpret_cast<const float2*>(image_ptr(d_basis, p.layout.lagw));
+  a.Dpad = p.Dpad;
+  a.prow16 = image_ptr(d_basis, p.layout.prow16);
+  a.prow32 = reinterpret_cast<const float2*>(image_ptr(d_basis, p.layout.prow32));
+  a.gexp = reinterpret_cast<const float*>(image_ptr(d_basis, p.layout.gexp));
   a.stream = stream;
   return a;
 }
@@ -143,7 +147,7 @@ fcc_status fcc_plan_query(fcc_plan plan, fcc_plan_info* info) {
   info->precision = p.precision;
   info->method = p.method;
   info->basis_bytes = p.layout.total;
-  info->spectrum_bytes_per_frame = size_t(p.M) * p.F * p.spec_elem;
+  info->spectrum_bytes_per_frame = size_t(p.M) * (p.N / 2) * p.spec_elem;
   info->spectrum_elem_bytes = p.spec_elem;
   return FCC_OK;
 }
@@ -168,7 +172,7 @@ fcc_status fcc_workspace_bytes(fcc_plan plan, int64_t num_frames, size_t* bytes)
   if (!plan || !bytes) return set_error(FCC_ERR_INVALID_ARG, "NULL argument");
   if (num_frames < 0) return set_error(FCC_ERR_INVALID_ARG, "num_frames must be >= 0");
   const fcc::Plan& p = plan->p;
-  const size_t b = size_t(num_frames) * p.M * p.F * p.spec_elem;
+  const size_t b = size_t(num_frames) * p.M * (p.N / 2) * p.spec_elem;
   *bytes = (b + 255) & ~size_t(255);
   return FCC_OK;
 }
@@ -199,7 +203,7 @@ static fcc_status pair_stage(const fcc::Plan& p, const void* d_basis, const void
   fcc::PairArgs a = pair_args(p, d_basis, d_spec, T, stream);
   a.tdoa = d_tdoa;
   a.y = d_y;
-  const hipError_t e = fcc::launch_pair_valu(a);
+  const hipError_t e = fcc::pair_mfma_supported(a) ? fcc::launch_pair_mfma(a) : fcc::launch_pair_valu(a);
   if (e == hipErrorInvalidValue)
     return set_error(FCC_ERR_UNSUPPORTED, "shape outside the pair kernel's limits");
   return hip_status(e, "pair kernel launch");

@@ -30,6 +30,10 @@ struct PairArgs {
   const float* basis32;      // [D][N/4 + 1]
   const float* dict;         // [I][2D]   (2 Dc, -2 Ds)
   const float2* lagw;        // [I][F]    exp(j 2 pi f tau_i / N)
+  int Dpad;                  // D padded to the matrix-core tiles
+  const void* prow16;        // half2  [Dpad][N/2] full-length rows, slot pairs
+  const float2* prow32;      // float2 [Dpad][N/2]
+  const float* gexp;         // [Ipad][Dpad] G = Dc - Ds
   int32_t* tdoa;             // [T][P] or null
   float* y;                  // [T][P][I] or null
   hipStream_t stream;
@@ -37,5 +41,7 @@ struct PairArgs {
 
 hipError_t launch_stft_phat(const StftArgs& a);
 hipError_t launch_pair_valu(const PairArgs& a);
+bool pair_mfma_supported(const PairArgs& a);
+hipError_t launch_pair_mfma(const PairArgs& a);
 
 }  // namespace fcc

@@ -1,8 +1,9 @@
 // Pair stage, plain FP32 vector-ALU form (Sec. 4): the reference GPU
 // implementation of the low-rank path, and the direct eq. (2) comparator.
 //
-// One workgroup per frame.  The frame's M whitened spectra are decoded to FP32
-// into LDS together with the cropped bases p_hat (eq. 7).  One thread per
+// One workgroup per frame.  The frame's M whitened spectra (packed real
+// layout: slot 0 carries the DC and Nyquist bins) are decoded to FP32 bins
+// 0 .. N/2 in LDS, together with the cropped bases p_hat (eq. 7).  One thread per
 // pair forms R(f) = e_i(f) e_j(f)^* on the fly, folds it into x_s / x_d
 // (eq. 8), accumulates the coefficients z_k of eq. (9) in chunks of eight
 // components, adds each chunk's share of y = 2 Re{U z} to I registers, and
@@ -26,8 +27,19 @@ __global__ __launch_bounds__(kThreads) void pair_valu_kernel(
   float2* sp = reinterpret_cast<float2*>(smem);
   float* bs = smem + 2 * M * F;
   const int64_t t = blockIdx.x;
-  const typename S::T* src = spec + t * (int64_t)M * F;
-  for (int i = threadIdx.x; i < M * F; i += kThreads) sp[i] = spec_decode<S>(src[i]);
+  const int NH = N / 2;
+  const typename S::T* src = spec + t * (int64_t)M * NH;
+  // packed real spectrum: slot 0 = (e(0), e(N/2)), slot f = e(f)
+  for (int i = threadIdx.x; i < M * NH; i += kThreads) {
+    const int mic = i / NH, f = i - mic * NH;
+    const float2 v = spec_decode<S>(src[i]);
+    if (f == 0) {
+      sp[mic * F] = make_float2(v.x, 0.f);
+      sp[mic * F + NH] = make_float2(v.y, 0.f);
+    } else {
+      sp[mic * F + f] = v;
+    }
+  }
   if (!GCC)
     for (int i = threadIdx.x; i < D * Bs; i += kThreads) bs[i] = basis[i];
   __syncthreads();

@@ -76,6 +76,32 @@ uint8_t to_e4m3(float f) {
   return uint8_t(sign | uint8_t((exp_unb + 7) << 3) | uint8_t(int(fl) - 8));
 }
 
+// cos and sin of 2 pi f / N, reduced to the first octant so that the values
+// at multiples of N/8 and the symmetries of the circle hold exactly.
+void unit_circle(int f, int N, double& cs, double& sn) {
+  f %= N;
+  if (f < 0) f += N;
+  const int q = (4 * f) / N;                  // quadrant
+  const int fr = f - q * (N / 4);             // 0 <= fr < N/4
+  double c, s;
+  if (2 * fr <= N / 4) {
+    const double a = 2.0 * kPi * fr / N;
+    c = std::cos(a);
+    s = std::sin(a);
+  } else {                                    // reflect about pi/4
+    const double a = 2.0 * kPi * (N / 4 - fr) / N;
+    c = std::sin(a);
+    s = std::cos(a);
+  }
+  if (fr == 0) { c = 1.0; s = 0.0; }
+  switch (q) {
+    case 0: cs = c; sn = s; break;
+    case 1: cs = -s; sn = c; break;
+    case 2: cs = -c; sn = -s; break;
+    default: cs = s; sn = -c; break;
+  }
+}
+
 }  // namespace
 
 void jacobi_one_sided(std::vector<double>& B, int n, int q, std::vector<double>& J) {
@@ -311,11 +337,20 @@ fcc_status build_plan(const fcc_config& cfg, Plan& pl, std::string& err) {
   L.pairs = off;   off = align256(off + 2 * size_t(pl.P));
   L.basis32 = off; off = align256(off + sizeof(float) * size_t(D) * (m + 1));
   L.dict = off;    off = align256(off + sizeof(float) * size_t(I) * 2 * D);
-  pl.Kpad = ((m + 1) + 31) / 32 * 32;
-  pl.Dpad = (D + 15) / 16 * 16;
-  L.basis16 = off; off = align256(off + sizeof(uint16_t) * size_t(pl.Dpad) * pl.Kpad);
-  L.basis8 = off;  off = align256(off + size_t(pl.Dpad) * pl.Kpad);
   L.lagw = off;    off = align256(off + 2 * sizeof(float) * size_t(I) * pl.F);
+  const int NH = pl.N / 2;
+  {
+    // the matrix-core pair kernel is instantiated for 1, 2, 3, 4, 6 or 8
+    // blocks of four components; pad D to one of those
+    int kb = (D + 3) / 4;
+    if (kb == 5) kb = 6;
+    if (kb == 7) kb = 8;
+    pl.Dpad = 4 * kb;
+  }
+  pl.Ipad = (I + 15) / 16 * 16;
+  L.prow32 = off;  off = align256(off + 2 * sizeof(float) * size_t(pl.Dpad) * NH);
+  L.prow16 = off;  off = align256(off + 2 * sizeof(uint16_t) * size_t(pl.Dpad) * NH);
+  L.gexp = off;    off = align256(off + sizeof(float) * size_t(pl.Ipad) * pl.Dpad);
   L.total = off;
   pl.image.assign(L.total, 0);
   unsigned char* img = pl.image.data();
@@ -325,8 +360,11 @@ fcc_status build_plan(const fcc_config& cfg, Plan& pl, std::string& err) {
   };
   for (int n = 0; n < pl.N; ++n) fput(L.window, n, 0.5 - 0.5 * std::cos(2.0 * kPi * n / pl.N));
   for (int f = 0; f < pl.F; ++f) {
-    fput(L.twiddle, 2 * f, std::cos(2.0 * kPi * f / pl.N));
-    fput(L.twiddle, 2 * f + 1, -std::sin(2.0 * kPi * f / pl.N));
+    // exp(-j 2 pi f / N) from the first octant, so the quarter points are exact
+    double cs, sn;
+    unit_circle(f, pl.N, cs, sn);
+    fput(L.twiddle, 2 * f, cs);
+    fput(L.twiddle, 2 * f + 1, -sn);
   }
   {
     int p = 0;
@@ -342,13 +380,24 @@ fcc_status build_plan(const fcc_config& cfg, Plan& pl, std::string& err) {
       fput(L.dict, size_t(i) * 2 * D + 2 * k, 2.0 * pl.dc[size_t(i) * D + k]);
       fput(L.dict, size_t(i) * 2 * D + 2 * k + 1, -2.0 * pl.ds[size_t(i) * D + k]);
     }
+  // full-length rows: p_k(f) = p_hat_k(f) for f <= N/4, +-p_hat_k(N/2 - f) above
+  auto prow = [&](int k, int f) {
+    const double* ph = &pl.p_hat[size_t(k) * (m + 1)];
+    if (f <= m) return ph[f];
+    return (pl.is_sym[k] ? 1.0 : -1.0) * ph[pl.N / 2 - f];
+  };
   for (int k = 0; k < D; ++k)
-    for (int f = 0; f <= m; ++f) {
-      const float v = float(pl.p_hat[size_t(k) * (m + 1) + f]);
-      const uint16_t h = pl.precision == FCC_FP16 ? to_fp16(v) : to_bf16(v);
-      std::memcpy(img + L.basis16 + 2 * (size_t(k) * pl.Kpad + f), &h, 2);
-      img[L.basis8 + size_t(k) * pl.Kpad + f] = to_e4m3(v);
+    for (int f = 0; f < NH; ++f) {
+      const double lo = prow(k, f), hi = (f == 0) ? prow(k, NH) : lo;
+      fput(L.prow32, 2 * (size_t(k) * NH + f), lo);
+      fput(L.prow32, 2 * (size_t(k) * NH + f) + 1, hi);
+      const uint16_t hlo = to_fp16(float(lo)), hhi = to_fp16(float(hi));
+      std::memcpy(img + L.prow16 + 4 * (size_t(k) * NH + f), &hlo, 2);
+      std::memcpy(img + L.prow16 + 4 * (size_t(k) * NH + f) + 2, &hhi, 2);
     }
+  for (int i = 0; i < I; ++i)
+    for (int k = 0; k < D; ++k)
+      fput(L.gexp, size_t(i) * pl.Dpad + k, pl.dc[size_t(i) * D + k] - pl.ds[size_t(i) * D + k]);
   for (int i = 0; i < I; ++i) {
     const double tau = double(i) / pl.r - pl.tau_max;
     for (int f = 0; f < pl.F; ++f) {

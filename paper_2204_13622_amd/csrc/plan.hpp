@@ -18,9 +18,13 @@ struct ImageLayout {
   size_t pairs = 0;       // uint8 [P][2]        (i, j), lexicographic
   size_t basis32 = 0;     // float [D][Bs]       p_hat rows, Bs = N/4 + 1
   size_t dict = 0;        // float [I][2D]       (2 Dc, -2 Ds) interleaved per k
-  size_t basis16 = 0;     // uint16 [Dpad][Kpad] p_hat in the plan's 16-bit type
-  size_t basis8 = 0;      // uint8 [Dpad][Kpad]  p_hat in e4m3
   size_t lagw = 0;        // float2 [I][F]       exp(j 2 pi f tau_i / N) (GCC)
+  // matrix-core pair stage: full-length rows p_k(f), f = 0 .. N/2, as pairs
+  // matching the packed spectrum slots: slot 0 -> (p_k(0), p_k(N/2)),
+  // slot f -> (p_k(f), p_k(f)); rows k >= D are zero.
+  size_t prow32 = 0;      // float2 [Dpad][N/2]
+  size_t prow16 = 0;      // half2  [Dpad][N/2]
+  size_t gexp = 0;        // float [Ipad][Dpad]  G(tau_i, k) = Dc - Ds; zero padded
   size_t total = 0;
 };
 
@@ -43,7 +47,7 @@ struct Plan {
   // packed device image
   ImageLayout layout;
   std::vector<unsigned char> image;
-  int Kpad = 0, Dpad = 0;           // padded MFMA operand shapes
+  int Dpad = 0, Ipad = 0;           // D and I rounded up to the MFMA tiles (4, 16)
   int spec_elem = 8;                // bytes per complex spectrum element
 };
 

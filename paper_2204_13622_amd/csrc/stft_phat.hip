@@ -9,11 +9,21 @@
 // packed as N/2 complex values z[n] = x[2n] + j x[2n+1], transformed by a
 // radix-2 Stockham FFT in LDS, and split into the N/2 + 1 bins of the real
 // transform.  Twiddles come from the plan's FP64-computed table.
+//
+// Output layout ("packed real spectrum"): N/2 complex slots per microphone;
+// slot 0 holds (e(0), e(N/2)), both real, slot f holds e(f) for 0 < f < N/2.
 #include "device_common.hpp"
 #include "kernels.hpp"
 
 namespace fcc {
 namespace {
+
+// PHAT of a real bin: its sign, or 0 (the squared-magnitude rule of the
+// complex bins, applied to a real value).
+__device__ __forceinline__ float phat_real(float x) {
+  if (x * x < 1.17549435e-38f) return 0.f;
+  return x > 0.f ? 1.f : -1.f;
+}
 
 template <int N, class S>
 __global__ __launch_bounds__(64) void stft_phat_kernel(
@@ -55,18 +65,25 @@ __global__ __launch_bounds__(64) void stft_phat_kernel(
   }
 
   // X(f) = E(f) + W^f O(f), E = (Z(f) + Z*(NH - f)) / 2, O = (Z(f) - Z*(NH - f)) / 2j
-  typename S::T* dst = out + bid * F;
-  for (int f = lane; f < F; f += 64) {
-    const float2 zf = buf[cur][f & (NH - 1)];
-    const float2 zr = buf[cur][(NH - f) & (NH - 1)];
-    const float2 e = make_float2(0.5f * (zf.x + zr.x), 0.5f * (zf.y - zr.y));
-    const float2 o = make_float2(0.5f * (zf.y + zr.y), -0.5f * (zf.x - zr.x));  // (Z - Z*) / 2j
-    const float2 X = cadd(e, cmul(tw[f], o));
-    const float n2 = X.x * X.x + X.y * X.y;
-    float2 v = make_float2(0.f, 0.f);
-    if (n2 >= 1.17549435e-38f) {
-      const float s = rsqrtf(n2);
-      v = make_float2(X.x * s, X.y * s);
+  typename S::T* dst = out + bid * NH;
+  for (int f = lane; f < NH; f += 64) {
+    float2 v;
+    if (f == 0) {
+      // X(0) = Re Z(0) + Im Z(0), X(N/2) = Re Z(0) - Im Z(0); both real
+      const float2 z0 = buf[cur][0];
+      v = make_float2(phat_real(z0.x + z0.y), phat_real(z0.x - z0.y));
+    } else {
+      const float2 zf = buf[cur][f];
+      const float2 zr = buf[cur][NH - f];
+      const float2 e = make_float2(0.5f * (zf.x + zr.x), 0.5f * (zf.y - zr.y));
+      const float2 o = make_float2(0.5f * (zf.y + zr.y), -0.5f * (zf.x - zr.x));  // (Z - Z*) / 2j
+      const float2 X = cadd(e, cmul(tw[f], o));
+      const float n2 = X.x * X.x + X.y * X.y;
+      v = make_float2(0.f, 0.f);
+      if (n2 >= 1.17549435e-38f) {
+        const float s = rsqrtf(n2);
+        v = make_float2(X.x * s, X.y * s);
+      }
     }
     dst[f] = spec_encode<S>(v);
   }

@@ -76,7 +76,7 @@ def test_plan_query(fcc):
     assert (p.M, p.P, p.N, p.F, p.tau_max, p.I, p.rank) == (16, 120, 512, 257, 5, 11, 6)
     assert (p.info.rank_sym, p.info.rank_anti) == (3, 3)
     assert p.num_frames(960000) == 7497 and p.num_frames(511) == 0 and p.num_frames(512) == 1
-    assert p.info.spectrum_bytes_per_frame == 16 * 257 * 8
+    assert p.info.spectrum_bytes_per_frame == 16 * 256 * 8     # packed: N/2 slots
     assert p.workspace_bytes(7497) % 256 == 0
     assert fcc.Plan(square_array(0.05), 16000.0, precision="bf16").info.spectrum_elem_bytes == 4
     assert fcc.Plan(square_array(0.05), 16000.0, precision="fp8").info.spectrum_elem_bytes == 2

@@ -43,9 +43,9 @@ def _dev(torch, x):
 
 
 def _oracle_spec_tensor(torch, X, dtype):
-    """Oracle-whitened spectra e = X / |X| as a [T, M, F, 2] device tensor."""
-    e = O.phat(X)
-    arr = np.stack([e.real, e.imag], axis=-1).astype(np.float32)
+    """Oracle-whitened spectra e = X / |X| as a packed [T, M, N/2, 2] device tensor."""
+    from paper_2204_13622_amd import Plan
+    arr = Plan.pack_spectrum(O.phat(X)).astype(np.float32)
     return torch.from_numpy(arr).cuda().to(dtype).contiguous()
 
 
@@ -74,8 +74,7 @@ def test_spectra_fp32(torch, fcc, config, seconds):
     torch.cuda.synchronize()
     X = O.stft(rec.x, rec.N, rec.hop)
     e_ref = O.phat(X)
-    g = spec.cpu().numpy()
-    e_gpu = g[..., 0] + 1j * g[..., 1]
+    e_gpu = fcc.Plan.unpack_spectrum(spec.cpu().numpy())
     assert e_gpu.shape == e_ref.shape
     mag = np.abs(X)
     rms = np.sqrt((mag ** 2).mean(-1, keepdims=True))
@@ -269,3 +268,39 @@ def test_precision_modes(torch, fcc, precision, min_agree, max_err):
     assert rep["agreement"] >= min_agree
     assert e.max() <= max_err
     assert rep["mismatch_qualified"] == 0
+
+
+# ------------------------------------------- matrix-core pair stage (16-bit) --
+
+def _quantized_reference(X, dtype_np, B):
+    """Oracle correlation of the spectra exactly as the GPU receives them:
+    e = X / |X| rounded to the storage type, products formed in FP64."""
+    from paper_2204_13622_amd import Plan
+    packed = Plan.pack_spectrum(O.phat(X)).astype(dtype_np).astype(np.float64)
+    e = Plan.unpack_spectrum(packed)
+    pr = O.mic_pairs(e.shape[1])
+    R = np.stack([e[:, i] * np.conj(e[:, j]) for i, j in pr], axis=1)
+    return packed, O.fcc_corr(R, B)
+
+
+@pytest.mark.parametrize("config,seconds,D,M", [(2, 1.0, 6, None), (2, 1.0, 11, None),
+                                                (3, 0.3, 15, None), (3, 0.3, 29, None),
+                                                (5, 1.0, 5, None), (2, 1.0, 9, 5), (1, 1.0, 9, None)])
+def test_mfma_pair_stage_fp16(torch, fcc, config, seconds, D, M):
+    _say(f"matrix-core pair stage fp16 config {config} D={D} M={M}")
+    rec = make_recording(config, seconds=seconds, M=M) if M else make_recording(config, seconds=seconds)
+    p = _plan(fcc, rec, D, precision="fp16")
+    X = O.stft(rec.x, rec.N, rec.hop)
+    B = O.fcc_basis(rec.N, p.tau_max, D)
+    packed, y_ref = _quantized_reference(X, np.float16, B)
+    spec = torch.from_numpy(packed.astype(np.float16)).cuda().contiguous()
+    y = p.correlation(spec).cpu().numpy()
+    t = p.tdoa_from_spectra(spec).cpu().numpy()
+    e = corr_errors(y, y_ref)
+    print(f"fp16 operands: max rel corr err {e.max():.3e}, mean {e.mean():.3e}", flush=True)
+    # FP16 operands carry 2^-11 relative rounding; sums over N terms of unit
+    # size against a peak of order N keep the relative error near 1e-3
+    assert e.max() < 5e-3
+    rep = tdoa_report(t, y_ref, p.tau_max, 5e-3)
+    assert rep["mismatch_qualified"] == 0, rep
+    assert rep["invalid_elsewhere"] == 0, rep
