@@ -37,7 +37,21 @@ def parse_args():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--seed", type=int, default=2000)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run plain device copies of this many MiB (counter calibration)")
     return ap.parse_args()
+
+
+def calibrate_copy(mib: int, steps: int):
+    """A plain copy of known size, for scaling the HBM byte counters."""
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(steps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration_copy_bytes": n * 4, "launches": steps}), flush=True)
 
 
 def time_loop(torch, fn, steps):
@@ -113,6 +127,9 @@ def main():
         print("bench.py measures one GPU only: the TDoA path is data-parallel over frames and "
               "this build does not shard it across GPUs; run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy, args.steps)
+        return
 
     import numpy as np
     import torch

@@ -108,8 +108,8 @@ typedef struct {
 
 /* Validates the configuration and computes, on the host in FP64, everything a
  * geometry needs (Sec. 4, Fig. 2 "computed offline"): tau_max, the lag grid,
- * the cropped bases p_hat_k (eq. 7) and the dictionary, the analysis window
- * and the DFT twiddles.  No device call is made.
+ * the cropped bases p_hat_k (eq. 7) and the dictionary, and the DFT
+ * twiddles.  No device call is made.
  * Errors: FCC_ERR_INVALID_ARG (M < 2, non-power-of-two N, hop <= 0,
  * tau_max >= N/4, rank outside [0, I], fs or c <= 0, null pointers),
  * FCC_ERR_UNSUPPORTED (interp != 1, alpha != 1, M > 32),
@@ -121,7 +121,7 @@ void fcc_plan_destroy(fcc_plan plan);
 
 fcc_status fcc_plan_query(fcc_plan plan, fcc_plan_info* info);
 
-/* Copies the plan's packed tables (window, twiddles, bases, dictionary) into
+/* Copies the plan's packed tables (DFT twiddles, bases, dictionary) into
  * d_basis, a caller-owned device buffer of info.basis_bytes bytes, aligned to
  * 256 bytes.  Enqueued on `stream`; the host tables stay owned by the plan. */
 fcc_status fcc_plan_upload(fcc_plan plan, void* d_basis, hipStream_t stream);

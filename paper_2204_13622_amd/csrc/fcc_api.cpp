@@ -87,7 +87,6 @@ fcc_status run_spectra(const fcc::Plan& p, const void* d_basis, const float* d_x
   a.N = p.N;
   a.hop = p.hop;
   a.precision = p.precision;
-  a.window = reinterpret_cast<const float*>(image_ptr(d_basis, p.layout.window));
   a.twiddle = reinterpret_cast<const float2*>(image_ptr(d_basis, p.layout.twiddle));
   a.out = d_spec;
   a.stream = stream;

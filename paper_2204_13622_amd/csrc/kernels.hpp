@@ -14,8 +14,7 @@ struct StftArgs {
   int64_t T;                 // frames
   int M, N, hop;
   fcc_precision precision;
-  const float* window;       // [N]
-  const float2* twiddle;     // [N/2 + 1]
+  const float2* twiddle;     // [N] exp(-j 2 pi f / N)
   void* out;                 // [T][M][N/2 + 1] complex, storage format
   hipStream_t stream;
 };

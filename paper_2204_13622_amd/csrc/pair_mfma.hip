@@ -17,7 +17,8 @@
 // work left to save here.  The expansion y = 2 Re{U z} becomes
 //   y_ij(tau) = sum_k G(tau, k) H_k(i, j) + G(-tau, k) H_k(j, i),  G = Dc - Ds.
 //
-// Tiles: one wavefront per frame.  A 16x16x32 MFMA tile has rows
+// Tiles: one wavefront per frame, which first stages the frame's spectra
+// into its LDS slab as FP16 pairs.  A 16x16x32 MFMA tile has rows
 // (k, i) = (4 kb + row / 4, 4 ib + row % 4) and columns j = 0 .. 15, so its
 // output register q of lane (g, col) holds H_{4kb+g}(4ib+q, col); that register
 // is directly the B operand of a 16x16x4 FP32 MFMA over k, which applies G.
@@ -33,52 +34,63 @@ typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef float f2 __attribute__((ext_vector_type(2)));
 
-constexpr int kWaves = 4;
 constexpr int kYStride = 16 * 16 + 4;   // floats per lag row; the pad spreads LDS banks
 
-// Four packed complex slots as eight FP16 values (re, im, re, im, ...).
-template <class S> __device__ __forceinline__ h8 load8(const typename S::T* p);
+// Four packed complex slots as four FP16 pairs (re, im), from storage.
+template <class S> __device__ __forceinline__ uint4 load4(const typename S::T* p);
 
-template <> __device__ __forceinline__ h8 load8<SpecF16>(const uint32_t* p) {
-  const uint4 v = *reinterpret_cast<const uint4*>(p);
-  return __builtin_bit_cast(h8, v);
+template <> __device__ __forceinline__ uint4 load4<SpecF16>(const uint32_t* p) {
+  return *reinterpret_cast<const uint4*>(p);
 }
-template <> __device__ __forceinline__ h8 load8<SpecBF16>(const uint32_t* p) {
-  const uint4 v = *reinterpret_cast<const uint4*>(p);
-  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-  h8 out;
-#pragma unroll
-  for (int c = 0; c < 4; ++c) {
-    out[2 * c] = (_Float16)__uint_as_float(w[c] << 16);
-    out[2 * c + 1] = (_Float16)__uint_as_float(w[c] & 0xffff0000u);
-  }
-  return out;
+__device__ __forceinline__ uint32_t pack_h2(float lo, float hi) {
+  const _Float16 a = (_Float16)lo, b = (_Float16)hi;
+  return (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
 }
-template <> __device__ __forceinline__ h8 load8<SpecE4M3>(const uint16_t* p) {
+template <> __device__ __forceinline__ uint4 load4<SpecBF16>(const uint32_t* p) {
+  const uint4 v = *reinterpret_cast<const uint4*>(p);
+  // bf16 -> f32 is a shift; f32 -> f16 is exact for the unit-modulus range
+  auto cv = [](uint32_t w) { return pack_h2(__uint_as_float(w << 16), __uint_as_float(w & 0xffff0000u)); };
+  return make_uint4(cv(v.x), cv(v.y), cv(v.z), cv(v.w));
+}
+template <> __device__ __forceinline__ uint4 load4<SpecE4M3>(const uint16_t* p) {
   const uint2 v = *reinterpret_cast<const uint2*>(p);
-  h8 out;
   const f2 a = __builtin_amdgcn_cvt_pk_f32_fp8((int)v.x, false);
   const f2 b = __builtin_amdgcn_cvt_pk_f32_fp8((int)v.x, true);
   const f2 c = __builtin_amdgcn_cvt_pk_f32_fp8((int)v.y, false);
   const f2 d = __builtin_amdgcn_cvt_pk_f32_fp8((int)v.y, true);
-  out[0] = (_Float16)a.x; out[1] = (_Float16)a.y;
-  out[2] = (_Float16)b.x; out[3] = (_Float16)b.y;
-  out[4] = (_Float16)c.x; out[5] = (_Float16)c.y;
-  out[6] = (_Float16)d.x; out[7] = (_Float16)d.y;
-  return out;
+  return make_uint4(pack_h2(a.x, a.y), pack_h2(b.x, b.y), pack_h2(c.x, c.y), pack_h2(d.x, d.y));
 }
 
-template <class S, int KB, int TT, bool WRITE_Y>
-__global__ __launch_bounds__(64 * kWaves) void pair_mfma_kernel(
+// Memory ordering between the lanes of one wavefront (LDS written by some
+// lanes, then read by others): a scheduling barrier fenced at wavefront scope.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+constexpr int kPrefetch = 16;   // rounds of 16-byte chunks per lane in flight (16 KB per wavefront)
+
+template <class S, int KB, int TT, bool WRITE_Y, int kWaves>
+__global__ __launch_bounds__(64 * kWaves, 2) void pair_mfma_kernel(
     const typename S::T* __restrict__ spec, int64_t T, int M, int P, int NH, int I, int tau_max,
-    const uint32_t* __restrict__ prow16, const float* __restrict__ gexp,
+    int slab_words, const uint32_t* __restrict__ prow16, const float* __restrict__ gexp,
     const uint8_t* __restrict__ pairs, int32_t* __restrict__ tdoa, float* __restrict__ yout) {
-  extern __shared__ float ybuf_all[];
+  extern __shared__ uint32_t lds_all[];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int g = lane >> 4, col = lane & 15;
-  float* ybuf = ybuf_all + wave * I * kYStride;
+  constexpr int Dp = 4 * KB;
+  // block-wide: the basis rows p_k (FP16 pairs per slot), then one slab per
+  // wavefront holding first the frame's spectra as FP16 pairs (16 rows of
+  // NH + 4 slots; rows of absent microphones are zero; the pad spreads rows
+  // over the LDS banks) and, after the projection, the lag rows Y
+  uint32_t* ptab = lds_all;
+  uint32_t* slab = lds_all + Dp * NH + wave * slab_words;
+  float* ybuf = reinterpret_cast<float*>(slab);
+  const int row = NH + 4;
   const int IB = (M + 3) >> 2;
-  const int Dp = 4 * KB;
+  for (int c = threadIdx.x; c < Dp * NH / 4; c += 64 * kWaves)
+    reinterpret_cast<uint4*>(ptab)[c] = reinterpret_cast<const uint4*>(prow16)[c];
 
   // A operands of the expansion: G(tau = 16 tt + col, k = 4 kb + g)
   float gx[TT][KB];
@@ -86,23 +98,63 @@ __global__ __launch_bounds__(64 * kWaves) void pair_mfma_kernel(
   for (int tt = 0; tt < TT; ++tt)
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb) gx[tt][kb] = gexp[(16 * tt + col) * Dp + 4 * kb + g];
+  __syncthreads();
 
-  const int64_t t = (int64_t)blockIdx.x * kWaves + wave;
-  const bool active = t < T;
-  if (active) {
+  // a frame is M * NH / 4 chunks of 16 bytes (4 slots); chunk c is slots
+  // 4 (c % (NH/4)) .. +3 of microphone c / (NH/4)
+  const int lg_row = 31 - __builtin_clz(NH / 4);
+  const int chunks = M * (NH / 4);
+  const int rounds = chunks >> 6;              // full rounds of 64 chunks
+  const int64_t stride = (int64_t)gridDim.x * kWaves;
+  int64_t t = (int64_t)blockIdx.x * kWaves + wave;
+
+  uint4 pre[kPrefetch];                        // first kPrefetch rounds, in flight
+  auto prefetch = [&](int64_t tf) {
+    const typename S::T* base = spec + tf * (int64_t)M * NH;
+#pragma unroll
+    for (int u = 0; u < kPrefetch; ++u)
+      if (u < rounds) pre[u] = load4<S>(base + 4 * (lane + 64 * u));
+  };
+  if (t < T) prefetch(t);
+
+  const h8 sgn = {-1, 1, -1, 1, -1, 1, -1, 1};
+  const int micA = col & 3;
+  const int nsteps = NH / 16;
+
+  for (; t < T; t += stride) {
+    // ---- stage the frame into the slab --------------------------------------
+    const typename S::T* base = spec + t * (int64_t)M * NH;
+#pragma unroll
+    for (int u = 0; u < kPrefetch; ++u) {
+      if (u < rounds) {
+        const int c = lane + 64 * u;
+        const int mic = c >> lg_row, q = c & ((NH / 4) - 1);
+        *reinterpret_cast<uint4*>(slab + mic * row + 4 * q) = pre[u];
+      }
+    }
+    for (int c = lane + 64 * (rounds < kPrefetch ? rounds : kPrefetch); c < chunks; c += 64) {
+      const uint4 v = load4<S>(base + 4 * c);
+      const int mic = c >> lg_row, q = c & ((NH / 4) - 1);
+      *reinterpret_cast<uint4*>(slab + mic * row + 4 * q) = v;
+    }
+    for (int c = M * row + lane * 4; c < 16 * row; c += 256)   // absent microphones
+      *reinterpret_cast<uint4*>(slab + c) = make_uint4(0, 0, 0, 0);
+    wave_sync();
+    if (t + stride < T) prefetch(t + stride);   // next frame flies during this one
+
+    // ---- projection: H_k = (p_k . E) R^T on 16x16x32 FP16 tiles ------------
     f4 acc[KB][4];
 #pragma unroll
     for (int kb = 0; kb < KB; ++kb)
 #pragma unroll
       for (int ib = 0; ib < 4; ++ib) acc[kb][ib] = f4{0.f, 0.f, 0.f, 0.f};
 
-    const typename S::T* base = spec + t * (int64_t)M * NH;
-    const int micA = col & 3;
-    const h8 zero8 = {0, 0, 0, 0, 0, 0, 0, 0};
-    const h8 sgn = {-1, 1, -1, 1, -1, 1, -1, 1};
-    for (int s = 0; s < NH / 16; ++s) {
-      const int slot = 16 * s + 4 * g;
-      const h8 raw = (col < M) ? load8<S>(base + col * NH + slot) : zero8;
+    const uint32_t* own = slab + col * row + 4 * g;
+    const uint32_t* amic = slab + micA * row + 4 * g;
+    const uint32_t* prow = ptab + (col >> 2) * NH + 4 * g;
+    for (int s = 0; s < nsteps; ++s) {
+      const int off = 16 * s;
+      const h8 raw = __builtin_bit_cast(h8, *reinterpret_cast<const uint4*>(own + off));
       // B: the rotated spectrum (a - b, a + b) of microphone `col`; the packed
       // DC / Nyquist slot holds two real bins and enters unrotated.
       const h8 sw = __builtin_shufflevector(raw, raw, 1, 0, 3, 2, 5, 4, 7, 6);
@@ -113,29 +165,25 @@ __global__ __launch_bounds__(64 * kWaves) void pair_mfma_kernel(
       }
       h8 Am[4];
 #pragma unroll
-      for (int ib = 0; ib < 4; ++ib) {
-        const int mic = 4 * ib + micA;
-        Am[ib] = (ib < IB && mic < M) ? load8<S>(base + mic * NH + slot) : zero8;
-      }
+      for (int ib = 0; ib < 4; ++ib)
+        Am[ib] = __builtin_bit_cast(h8, *reinterpret_cast<const uint4*>(amic + 4 * ib * row + off));
 #pragma unroll
       for (int kb = 0; kb < KB; ++kb) {
-        const int k = 4 * kb + (col >> 2);
-        const h8 pk = __builtin_bit_cast(h8, *reinterpret_cast<const uint4*>(prow16 + (size_t)k * NH + slot));
+        const h8 pk = __builtin_bit_cast(h8, *reinterpret_cast<const uint4*>(prow + 4 * kb * NH + off));
 #pragma unroll
-        for (int ib = 0; ib < 4; ++ib) {
+        for (int ib = 0; ib < 4; ++ib)
           if (ib < IB) acc[kb][ib] = __builtin_amdgcn_mfma_f32_16x16x32_f16(Am[ib] * pk, B, acc[kb][ib], 0, 0, 0);
-        }
       }
     }
+    wave_sync();   // every lane has read the spectra; the slab now takes Y
 
-    // expansion: Y_i(tau, j) = sum_k G(tau, k) H_k(i, j), one 16x16x4 chain per mic
+    // ---- expansion: Y_i(tau, j) = sum_k G(tau, k) H_k(i, j) --------------------
 #pragma unroll
     for (int ib = 0; ib < 4; ++ib) {
       if (ib >= IB) continue;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int i = 4 * ib + q;
-        if (i >= M) continue;
 #pragma unroll
         for (int tt = 0; tt < TT; ++tt) {
           f4 Y = {0.f, 0.f, 0.f, 0.f};
@@ -143,49 +191,83 @@ __global__ __launch_bounds__(64 * kWaves) void pair_mfma_kernel(
           for (int kb = 0; kb < KB; ++kb)
             Y = __builtin_amdgcn_mfma_f32_16x16x4f32(gx[tt][kb], acc[kb][ib][q], Y, 0, 0, 0);
 #pragma unroll
-          for (int qq = 0; qq < 4; ++qq) {
-            const int tau = 16 * tt + 4 * g + qq;
-            if (tau < I) ybuf[tau * kYStride + i * 16 + col] = Y[qq];
-          }
+          for (int qq = 0; qq < 4; ++qq)   // rows tau >= I are padding, never read
+            ybuf[(16 * tt + 4 * g + qq) * kYStride + i * 16 + col] = Y[qq];
         }
       }
     }
-  }
-  __syncthreads();
-  if (active) {
+    wave_sync();
+
+    // ---- per pair: y_ij(tau) = Y_i(tau, j) + Y_j(-tau, i); first-index argmax
     for (int p = lane; p < P; p += 64) {
       const int i = pairs[2 * p], j = pairs[2 * p + 1];
-      const int64_t row = t * P + p;
-      float best = 0.f;
+      const int64_t orow = t * P + p;
+      const float* ya = ybuf + i * 16 + j;
+      const float* yb = ybuf + (I - 1) * kYStride + j * 16 + i;
+      float best = ya[0] + yb[0];
       int bi = 0;
-      for (int tau = 0; tau < I; ++tau) {
-        const float v = ybuf[tau * kYStride + i * 16 + j] + ybuf[(I - 1 - tau) * kYStride + j * 16 + i];
-        if (WRITE_Y) yout[row * I + tau] = v;
-        if (tau == 0 || v > best) {
+      if (WRITE_Y) yout[orow * I] = best;
+      for (int tau = 1; tau < I; ++tau) {
+        const float v = ya[tau * kYStride] + yb[-tau * kYStride];
+        if (WRITE_Y) yout[orow * I + tau] = v;
+        if (v > best) {
           best = v;
           bi = tau;
         }
       }
-      if (!WRITE_Y) tdoa[row] = bi - tau_max;
+      if (!WRITE_Y) tdoa[orow] = bi - tau_max;
     }
+    wave_sync();   // the slab is rewritten by the next frame
   }
 }
 
-template <class S, int KB, int TT, bool WY>
-hipError_t launch4(const PairArgs& a) {
-  auto k = pair_mfma_kernel<S, KB, TT, WY>;
-  const size_t lds = sizeof(float) * size_t(kWaves) * a.I * kYStride;
+// 32-bit words of LDS one wavefront needs: the staged spectra or the lag rows
+int slab_words(const PairArgs& a) {
+  const int spec_words = 16 * (a.N / 2 + 4);
+  const int y_words = ((a.I + 15) / 16) * 16 * kYStride;
+  return spec_words > y_words ? spec_words : y_words;
+}
+
+size_t lds_bytes(const PairArgs& a, int waves) {
+  return sizeof(uint32_t) * (size_t(a.Dpad) * (a.N / 2) + size_t(waves) * slab_words(a));
+}
+
+// wavefronts per block: four when the block's LDS fits, else two
+int block_waves(const PairArgs& a) {
+  if (lds_bytes(a, 4) <= 160 * 1024) return 4;
+  if (lds_bytes(a, 2) <= 160 * 1024) return 2;
+  return 0;
+}
+
+template <class S, int KB, int TT, bool WY, int WV>
+hipError_t launch5(const PairArgs& a) {
+  auto k = pair_mfma_kernel<S, KB, TT, WY, WV>;
+  const size_t lds = lds_bytes(a, WV);
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  const int64_t blocks = (a.T + kWaves - 1) / kWaves;
-  hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * kWaves), lds, a.stream,
+  // persistent wavefronts: enough blocks to fill the chip twice over, each
+  // wavefront walking the frames with a grid-sized stride
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
+  }
+  const int64_t need = (a.T + WV - 1) / WV;
+  const int64_t cap = int64_t(2) * cus * (4 / WV);
+  const int64_t blocks = need < cap ? need : cap;
+  hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * WV), lds, a.stream,
                      static_cast<const typename S::T*>(a.spec), a.T, a.M, a.P, a.N / 2, a.I,
-                     a.tau_max, reinterpret_cast<const uint32_t*>(a.prow16), a.gexp, a.pairs,
-                     a.tdoa, a.y);
+                     a.tau_max, slab_words(a), reinterpret_cast<const uint32_t*>(a.prow16), a.gexp,
+                     a.pairs, a.tdoa, a.y);
   return hipGetLastError();
+}
+
+template <class S, int KB, int TT, bool WY>
+hipError_t launch4(const PairArgs& a) {
+  return block_waves(a) == 4 ? launch5<S, KB, TT, WY, 4>(a) : launch5<S, KB, TT, WY, 2>(a);
 }
 
 template <class S, int KB>
@@ -215,7 +297,8 @@ bool pair_mfma_supported(const PairArgs& a) {
   const int kb = a.Dpad / 4;
   const bool kb_ok = a.Dpad % 4 == 0 && (kb == 1 || kb == 2 || kb == 3 || kb == 4 || kb == 6 || kb == 8);
   return a.method == FCC_METHOD_FCC && a.precision != FCC_FP32 && a.M <= 16 && a.N >= 32 &&
-         a.D <= a.Dpad && kb_ok && a.I <= 32;
+         (reinterpret_cast<uintptr_t>(a.spec) % 16) == 0 &&
+         a.D <= a.Dpad && kb_ok && a.I <= 32 && block_waves(a) > 0;
 }
 
 hipError_t launch_pair_mfma(const PairArgs& a) {

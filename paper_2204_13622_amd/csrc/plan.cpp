@@ -332,8 +332,7 @@ fcc_status build_plan(const fcc_config& cfg, Plan& pl, std::string& err) {
   pl.spec_elem = pl.precision == FCC_FP32 ? 8 : (pl.precision == FCC_FP8_E4M3 ? 2 : 4);
   ImageLayout& L = pl.layout;
   size_t off = 0;
-  L.window = off;  off = align256(off + sizeof(float) * pl.N);
-  L.twiddle = off; off = align256(off + 2 * sizeof(float) * pl.F);
+  L.twiddle = off; off = align256(off + 2 * sizeof(float) * pl.N);
   L.pairs = off;   off = align256(off + 2 * size_t(pl.P));
   L.basis32 = off; off = align256(off + sizeof(float) * size_t(D) * (m + 1));
   L.dict = off;    off = align256(off + sizeof(float) * size_t(I) * 2 * D);
@@ -358,8 +357,7 @@ fcc_status build_plan(const fcc_config& cfg, Plan& pl, std::string& err) {
     const float f = float(v);
     std::memcpy(img + base + 4 * i, &f, 4);
   };
-  for (int n = 0; n < pl.N; ++n) fput(L.window, n, 0.5 - 0.5 * std::cos(2.0 * kPi * n / pl.N));
-  for (int f = 0; f < pl.F; ++f) {
+  for (int f = 0; f < pl.N; ++f) {
     // exp(-j 2 pi f / N) from the first octant, so the quarter points are exact
     double cs, sn;
     unit_circle(f, pl.N, cs, sn);

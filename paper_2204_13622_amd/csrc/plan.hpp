@@ -13,8 +13,7 @@ namespace fcc {
 
 // Offsets (bytes) of the tables inside the device image; each is 256-aligned.
 struct ImageLayout {
-  size_t window = 0;      // float [N]           periodic Hann window
-  size_t twiddle = 0;     // float2 [N/2 + 1]    exp(-j 2 pi f / N)
+  size_t twiddle = 0;     // float2 [N]          exp(-j 2 pi f / N), full circle
   size_t pairs = 0;       // uint8 [P][2]        (i, j), lexicographic
   size_t basis32 = 0;     // float [D][Bs]       p_hat rows, Bs = N/4 + 1
   size_t dict = 0;        // float [I][2D]       (2 Dc, -2 Ds) interleaved per k

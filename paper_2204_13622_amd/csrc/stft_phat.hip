@@ -5,10 +5,16 @@
 //   R_ij / |R_ij| = (X_i / |X_i|) (X_j / |X_j|)^*,
 // so each bin is normalised once per microphone here instead of once per pair.
 //
-// One wavefront transforms one (frame, microphone): the N real samples are
-// packed as N/2 complex values z[n] = x[2n] + j x[2n+1], transformed by a
-// radix-2 Stockham FFT in LDS, and split into the N/2 + 1 bins of the real
-// transform.  Twiddles come from the plan's FP64-computed table.
+// The N real samples of a frame are packed as N/2 complex values
+// z[n] = w[2n] x[2n] + j w[2n+1] x[2n+1] and transformed by a mixed-radix
+// Stockham FFT: radix-16 butterflies held in registers, one LDS exchange per
+// pass (two passes for N = 512), in a buffer padded by one slot every 16.  A
+// transform uses N/32 lanes (one for N <= 32);
+// a 256-thread block runs 256 / lanes transforms over consecutive
+// (frame, microphone) pairs, so for M = 16 and N = 512 a block is one frame.
+// The split Z -> X(f) = E(f) + W^f O(f) of the real transform follows, then the
+// normalisation.  Twiddles (and the window, through its cosine) come from a
+// full-circle FP64-computed table staged in LDS.
 //
 // Output layout ("packed real spectrum"): N/2 complex slots per microphone;
 // slot 0 holds (e(0), e(N/2)), both real, slot f holds e(f) for 0 < f < N/2.
@@ -18,83 +24,229 @@
 namespace fcc {
 namespace {
 
-// PHAT of a real bin: its sign, or 0 (the squared-magnitude rule of the
-// complex bins, applied to a real value).
+constexpr int kThreads = 256;
+
+// exp(-j 2 pi m / 16), m = 0 .. 15 (cos and sin of multiples of pi/8)
+__device__ __forceinline__ float2 w16(int m) {
+  constexpr float c1 = 0.92387953251128674f, s1 = 0.38268343236508978f, c2 = 0.70710678118654752f;
+  switch (m & 15) {
+    case 0: return make_float2(1.f, 0.f);
+    case 1: return make_float2(c1, -s1);
+    case 2: return make_float2(c2, -c2);
+    case 3: return make_float2(s1, -c1);
+    case 4: return make_float2(0.f, -1.f);
+    case 5: return make_float2(-s1, -c1);
+    case 6: return make_float2(-c2, -c2);
+    case 7: return make_float2(-c1, -s1);
+    case 8: return make_float2(-1.f, 0.f);
+    case 9: return make_float2(-c1, s1);
+    case 10: return make_float2(-c2, c2);
+    case 11: return make_float2(-s1, c1);
+    case 12: return make_float2(0.f, 1.f);
+    case 13: return make_float2(s1, c1);
+    case 14: return make_float2(c2, c2);
+    default: return make_float2(c1, s1);
+  }
+}
+
+// v * exp(-j 2 pi M / 16) with the trivial rotations done exactly
+template <int M>
+__device__ __forceinline__ float2 rot16(float2 v) {
+  constexpr int m = M & 15;
+  if constexpr (m == 0) return v;
+  else if constexpr (m == 4) return make_float2(v.y, -v.x);
+  else if constexpr (m == 8) return make_float2(-v.x, -v.y);
+  else if constexpr (m == 12) return make_float2(-v.y, v.x);
+  else return cmul(v, w16(m));
+}
+
+// In-register DFT of R points (natural order in and out), radix-2
+// decimation in time with compile-time twiddles; R divides 16.  The R inputs
+// sit at u[0], u[S], u[2S], ... (stride S in registers).
+template <int R>
+struct Dft {
+  template <int S = 1>
+  __device__ __forceinline__ static void run(float2* u) {
+    Dft<R / 2>::template run<2 * S>(u);        // even-indexed inputs
+    Dft<R / 2>::template run<2 * S>(u + S);    // odd-indexed inputs
+    float2 out[R];
+#pragma unroll
+    for (int k = 0; k < R / 2; ++k) {
+      const float2 e = u[2 * S * k], o = u[2 * S * k + S];
+      const float2 t = twiddle(o, k);
+      out[k] = cadd(e, t);
+      out[k + R / 2] = csub(e, t);
+    }
+#pragma unroll
+    for (int k = 0; k < R; ++k) u[S * k] = out[k];
+  }
+  // o * exp(-j 2 pi k / R) = o * exp(-j 2 pi (16 k / R) / 16)
+  __device__ __forceinline__ static float2 twiddle(float2 o, int k) {
+    switch ((16 / R) * k) {
+      case 0: return rot16<0>(o);
+      case 1: return rot16<1>(o);
+      case 2: return rot16<2>(o);
+      case 3: return rot16<3>(o);
+      case 4: return rot16<4>(o);
+      case 5: return rot16<5>(o);
+      case 6: return rot16<6>(o);
+      default: return rot16<7>(o);
+    }
+  }
+};
+template <>
+struct Dft<1> {
+  template <int S = 1>
+  __device__ __forceinline__ static void run(float2*) {}
+};
+
+template <int NH>
+struct Radices {
+  static constexpr int R0 = NH >= 16 ? 16 : NH;        // first pass
+  static constexpr int rem0 = NH / R0;
+  static constexpr int R1 = rem0 >= 16 ? 16 : rem0;    // second pass (1 = none)
+  static constexpr int rem1 = rem0 / R1;
+  static constexpr int R2 = rem1;                      // third pass (1 = none)
+  static constexpr int LF = NH >= 16 ? NH / 16 : 1;    // lanes per transform
+};
+
+// Position of point n in a transform's LDS buffer: one pad slot after every
+// 16 points, so the stride-16 accesses of the passes spread over the banks.
+__device__ __forceinline__ int pidx(int n) { return n + (n >> 4); }
+
+// One LDS pass of radix R after P points have been combined; twp[r * P + k]
+// holds exp(-j 2 pi r k / (P R)).
+template <int R, int P, int NH, int LF>
+__device__ __forceinline__ void lds_pass(float2* buf, const float2* twp, int lf, bool active) {
+  constexpr int NB = NH / R;          // butterflies
+  constexpr int BPL = NB / LF;        // per lane
+  float2 u[BPL][R];
+  if (active) {
+#pragma unroll
+    for (int b = 0; b < BPL; ++b) {
+      const int i = lf + b * LF;
+#pragma unroll
+      for (int r = 0; r < R; ++r) u[b][r] = buf[pidx(i + r * NB)];
+    }
+  }
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int b = 0; b < BPL; ++b) {
+      const int i = lf + b * LF;
+      const int k = i % P;
+#pragma unroll
+      for (int r = 1; r < R; ++r) u[b][r] = cmul(u[b][r], twp[r * P + k]);
+      Dft<R>::run(u[b]);
+      const int j = (i - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[pidx(j + r * P)] = u[b][r];
+    }
+  }
+  __syncthreads();
+}
+
+// PHAT of one bin: X / |X|, or 0 when |X|^2 is below the smallest normal
+// float.  A real bin's PHAT is its sign.
+__device__ __forceinline__ float2 phat_complex(float2 X) {
+  const float n2 = X.x * X.x + X.y * X.y;
+  if (n2 < 1.17549435e-38f) return make_float2(0.f, 0.f);
+  const float s = rsqrtf(n2);
+  return make_float2(X.x * s, X.y * s);
+}
 __device__ __forceinline__ float phat_real(float x) {
   if (x * x < 1.17549435e-38f) return 0.f;
   return x > 0.f ? 1.f : -1.f;
 }
 
 template <int N, class S>
-__global__ __launch_bounds__(64) void stft_phat_kernel(
-    const float* __restrict__ x, int64_t ld, int M, int hop,
-    const float* __restrict__ window, const float2* __restrict__ twiddle,
-    typename S::T* __restrict__ out) {
+__global__ __launch_bounds__(kThreads) void stft_phat_kernel(
+    const float* __restrict__ x, int64_t ld, int M, int hop, int64_t nfft,
+    const float2* __restrict__ twiddle, typename S::T* __restrict__ out) {
   constexpr int NH = N / 2;
-  constexpr int F = NH + 1;
-  __shared__ float2 buf[2][NH];
-  __shared__ float2 tw[F];
-  const int lane = threadIdx.x;
-  const int64_t bid = blockIdx.x;                 // = t * M + m
-  const int mic = (int)(bid % M);
-  const int64_t t = bid / M;
-  const float* src = x + (int64_t)mic * ld + t * hop;
+  using RD = Radices<NH>;
+  constexpr int LF = RD::LF;
+  constexpr int FPB = kThreads / LF;                // transforms per block
+  constexpr int NHP = NH + NH / 16;                 // padded buffer length
+  constexpr int P1 = RD::R0, P2 = RD::R0 * RD::R1;
+  constexpr int T1 = RD::R1 > 1 ? RD::R1 * P1 : 1;  // twiddle table sizes of the LDS passes
+  constexpr int T2 = RD::R2 > 1 ? RD::R2 * P2 : 1;
+  __shared__ float2 tw[N];
+  __shared__ float2 tw1[T1];
+  __shared__ float2 tw2[T2];
+  __shared__ float2 data[FPB * NHP];
 
-  for (int f = lane; f < F; f += 64) tw[f] = twiddle[f];
-  for (int n = lane; n < NH; n += 64) {
-    const float a = src[2 * n] * window[2 * n];
-    const float b = src[2 * n + 1] * window[2 * n + 1];
-    buf[0][n] = make_float2(a, b);
-  }
+  const int slot = threadIdx.x / LF, lf = threadIdx.x % LF;
+  const int64_t b = (int64_t)blockIdx.x * FPB + slot;   // = t * M + m
+  const bool active = b < nfft;
+  for (int f = threadIdx.x; f < N; f += kThreads) tw[f] = twiddle[f];
+  if constexpr (RD::R1 > 1)
+    for (int e = threadIdx.x; e < T1; e += kThreads) {
+      const int r = e / P1, k = e % P1;
+      tw1[e] = twiddle[r * k * (N / (P1 * RD::R1))];
+    }
+  if constexpr (RD::R2 > 1)
+    for (int e = threadIdx.x; e < T2; e += kThreads) {
+      const int r = e / P2, k = e % P2;
+      tw2[e] = twiddle[r * k * (N / (P2 * RD::R2))];
+    }
   __syncthreads();
 
-  int cur = 0;
-#pragma unroll 1
-  for (int p = 1; p < NH; p <<= 1) {
-    const int tstride = N / (2 * p);
-    for (int i = lane; i < NH / 2; i += 64) {
-      const int k = i & (p - 1);
-      const float2 u0 = buf[cur][i];
-      const float2 u1 = cmul(buf[cur][i + NH / 2], tw[k * tstride]);
-      const int j = 2 * i - k;
-      buf[cur ^ 1][j] = cadd(u0, u1);
-      buf[cur ^ 1][j + p] = csub(u0, u1);
+  float2* buf = data + slot * NHP;
+  // first pass straight from memory: radix R0, no twiddles (p = 1)
+  {
+    constexpr int R = RD::R0, NB = NH / R;
+    float2 u[R];
+    if (active) {
+      const int mic = (int)(b % M);
+      const int64_t t = b / M;
+      const float* src = x + (int64_t)mic * ld + t * hop;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int n = lf + r * NB;
+        const float w0 = 0.5f - 0.5f * tw[2 * n].x;          // periodic Hann
+        const float w1 = 0.5f - 0.5f * tw[2 * n + 1].x;
+        u[r] = make_float2(w0 * src[2 * n], w1 * src[2 * n + 1]);
+      }
+      Dft<R>::run(u);
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[pidx(lf * R + r)] = u[r];
     }
-    cur ^= 1;
     __syncthreads();
   }
+  if constexpr (RD::R1 > 1) lds_pass<RD::R1, P1, NH, LF>(buf, tw1, lf, active);
+  if constexpr (RD::R2 > 1) lds_pass<RD::R2, P2, NH, LF>(buf, tw2, lf, active);
 
-  // X(f) = E(f) + W^f O(f), E = (Z(f) + Z*(NH - f)) / 2, O = (Z(f) - Z*(NH - f)) / 2j
-  typename S::T* dst = out + bid * NH;
-  for (int f = lane; f < NH; f += 64) {
-    float2 v;
+  if (!active) return;
+  // Real split: E = (Z(f) + Z*(NH - f)) / 2, O = (Z(f) - Z*(NH - f)) / 2j,
+  // X(f) = E + W^f O and X(NH - f) = conj(E - W^f O).
+  typename S::T* dst = out + b * NH;
+  for (int f = lf; f <= NH / 2; f += LF) {
     if (f == 0) {
       // X(0) = Re Z(0) + Im Z(0), X(N/2) = Re Z(0) - Im Z(0); both real
-      const float2 z0 = buf[cur][0];
-      v = make_float2(phat_real(z0.x + z0.y), phat_real(z0.x - z0.y));
-    } else {
-      const float2 zf = buf[cur][f];
-      const float2 zr = buf[cur][NH - f];
-      const float2 e = make_float2(0.5f * (zf.x + zr.x), 0.5f * (zf.y - zr.y));
-      const float2 o = make_float2(0.5f * (zf.y + zr.y), -0.5f * (zf.x - zr.x));  // (Z - Z*) / 2j
-      const float2 X = cadd(e, cmul(tw[f], o));
-      const float n2 = X.x * X.x + X.y * X.y;
-      v = make_float2(0.f, 0.f);
-      if (n2 >= 1.17549435e-38f) {
-        const float s = rsqrtf(n2);
-        v = make_float2(X.x * s, X.y * s);
-      }
+      const float2 z0 = buf[0];
+      dst[0] = spec_encode<S>(make_float2(phat_real(z0.x + z0.y), phat_real(z0.x - z0.y)));
+      continue;
     }
-    dst[f] = spec_encode<S>(v);
+    const float2 zf = buf[pidx(f)];
+    const float2 zr = buf[pidx(NH - f)];
+    const float2 e = make_float2(0.5f * (zf.x + zr.x), 0.5f * (zf.y - zr.y));
+    const float2 o = make_float2(0.5f * (zf.y + zr.y), -0.5f * (zf.x - zr.x));
+    const float2 wo = cmul(tw[f], o);
+    const float2 Xa = cadd(e, wo);
+    const float2 Xb = make_float2(e.x - wo.x, wo.y - e.y);
+    dst[f] = spec_encode<S>(phat_complex(Xa));
+    if (f != NH - f) dst[NH - f] = spec_encode<S>(phat_complex(Xb));
   }
 }
 
 template <int N, class S>
 hipError_t launch_n(const StftArgs& a) {
-  const int64_t blocks = a.T * a.M;
-  hipLaunchKernelGGL((stft_phat_kernel<N, S>), dim3((unsigned)blocks), dim3(64), 0, a.stream,
-                     a.x, a.ld, a.M, a.hop, a.window, a.twiddle,
-                     static_cast<typename S::T*>(a.out));
+  constexpr int FPB = kThreads / Radices<N / 2>::LF;
+  const int64_t nfft = a.T * a.M;
+  const int64_t blocks = (nfft + FPB - 1) / FPB;
+  hipLaunchKernelGGL((stft_phat_kernel<N, S>), dim3((unsigned)blocks), dim3(kThreads), 0, a.stream,
+                     a.x, a.ld, a.M, a.hop, nfft, a.twiddle, static_cast<typename S::T*>(a.out));
   return hipGetLastError();
 }
 
