@@ -165,11 +165,12 @@ def main():
     ms_stft = time_loop(torch, lambda: plan.spectra(x, out=spec_view), args.steps)
     ms_pair = time_loop(torch, lambda: plan.tdoa_from_spectra(spec_view, out=out), args.steps)
     kb = kernel_bytes(plan, rec.L, T)
-    workload = f"M16-circle5cm-fs16k-N512-hop128-60s"
+    workload = "M16-circle5cm-fs16k-N512-hop128-60s"
     dom = "pair" if ms_pair >= ms_stft else "stft_phat"
     dom_ms = ms_pair if dom == "pair" else ms_stft
     achieved = kb[dom] / (dom_ms * 1e-3) / 1e9
-    traffic = traffic_for("pair_valu.hip" if dom == "pair" else "stft_phat.hip", workload,
+    pair_file = "pair_valu.hip" if args.precision == "fp32" else "pair_mfma.hip"
+    traffic = traffic_for(pair_file if dom == "pair" else "stft_phat.hip", workload,
                           args.precision, args.rank)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

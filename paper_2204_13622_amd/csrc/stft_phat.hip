@@ -25,6 +25,7 @@ namespace fcc {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr unsigned kXcds = 8;       // accelerator complex dies of an MI355X
 
 // exp(-j 2 pi m / 16), m = 0 .. 15 (cos and sin of multiples of pi/8)
 __device__ __forceinline__ float2 w16(int m) {
@@ -176,8 +177,15 @@ __global__ __launch_bounds__(kThreads) void stft_phat_kernel(
   __shared__ float2 tw2[T2];
   __shared__ float2 data[FPB * NHP];
 
+  // Workgroups are dealt to the 8 XCDs round-robin; give each XCD one
+  // contiguous run of transforms so the 4x overlap of neighbouring frames is
+  // served from that XCD's L2 instead of HBM.
+  const unsigned nblk = gridDim.x;
+  const unsigned xcd = blockIdx.x % kXcds, local = blockIdx.x / kXcds;
+  const unsigned per = nblk / kXcds, extra = nblk % kXcds;     // blocks per XCD (first `extra` get one more)
+  const unsigned lblk = xcd * per + (xcd < extra ? xcd : extra) + local;
   const int slot = threadIdx.x / LF, lf = threadIdx.x % LF;
-  const int64_t b = (int64_t)blockIdx.x * FPB + slot;   // = t * M + m
+  const int64_t b = (int64_t)lblk * FPB + slot;   // = t * M + m
   const bool active = b < nfft;
   for (int f = threadIdx.x; f < N; f += kThreads) tw[f] = twiddle[f];
   if constexpr (RD::R1 > 1)
