@@ -73,6 +73,8 @@ fcc::PairArgs pair_args(const fcc::Plan& p, const void* d_basis, const void* d_s
   a.prow16 = image_ptr(d_basis, p.layout.prow16);
   a.prow32 = reinterpret_cast<const float2*>(image_ptr(d_basis, p.layout.prow32));
   a.gexp = reinterpret_cast<const float*>(image_ptr(d_basis, p.layout.gexp));
+  a.Dfold = p.Dfold;
+  a.pfold = reinterpret_cast<const float*>(image_ptr(d_basis, p.layout.pfold));
   a.stream = stream;
   return a;
 }
@@ -202,7 +204,10 @@ static fcc_status pair_stage(const fcc::Plan& p, const void* d_basis, const void
   fcc::PairArgs a = pair_args(p, d_basis, d_spec, T, stream);
   a.tdoa = d_tdoa;
   a.y = d_y;
-  const hipError_t e = fcc::pair_mfma_supported(a) ? fcc::launch_pair_mfma(a) : fcc::launch_pair_valu(a);
+  hipError_t e;
+  if (fcc::pair_mfma_supported(a)) e = fcc::launch_pair_mfma(a);
+  else if (p.precision == FCC_FP32 && fcc::pair_fold32_supported(a)) e = fcc::launch_pair_fold32(a);
+  else e = fcc::launch_pair_valu(a);
   if (e == hipErrorInvalidValue)
     return set_error(FCC_ERR_UNSUPPORTED, "shape outside the pair kernel's limits");
   return hip_status(e, "pair kernel launch");

@@ -33,6 +33,8 @@ struct PairArgs {
   const void* prow16;        // half2  [Dpad][N/2] full-length rows, slot pairs
   const float2* prow32;      // float2 [Dpad][N/2]
   const float* gexp;         // [Ipad][Dpad] G = Dc - Ds
+  int Dfold;                 // D padded to the FP32 fold kernel's register block
+  const float* pfold;        // [N/4 + 1][Dfold] p_hat transposed, zero beyond D
   int32_t* tdoa;             // [T][P] or null
   float* y;                  // [T][P][I] or null
   hipStream_t stream;
@@ -41,6 +43,8 @@ struct PairArgs {
 hipError_t launch_stft_phat(const StftArgs& a);
 hipError_t launch_pair_valu(const PairArgs& a);
 bool pair_mfma_supported(const PairArgs& a);
+bool pair_fold32_supported(const PairArgs& a);
+hipError_t launch_pair_fold32(const PairArgs& a);
 hipError_t launch_pair_mfma(const PairArgs& a);
 
 }  // namespace fcc

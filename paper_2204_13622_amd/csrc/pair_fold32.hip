@@ -1,0 +1,169 @@
+// Pair stage in FP32 on the vector ALU, in the folded form of the paper
+// (Sec. 4: eq. 8 fold, eq. 9 projection, y = 2 Re{U z}, argmax of Sec. 2).
+//
+// One workgroup per frame.  The frame's whitened spectra are unpacked to
+// FP32 bins 0 .. N/2 in LDS.  Lanes own pairs; the folded bins f < N/4 are
+// split between two groups of wavefronts, so within a wavefront every lane
+// visits the same bin and the basis values p_hat_k(f) are wavefront-uniform
+// (one scalar load of a contiguous row of the transposed table, no LDS
+// traffic).  Per bin a lane forms
+//   R(f) = e_i(f) e_j(f)^*,  R(N/2 - f),  x_s = R(f) + R(N/2 - f),  x_d = R(f) - R(N/2 - f)
+// and accumulates z_k += p_hat_k(f) x_s (symmetric k) or p_hat_k(f) x_d
+// (antisymmetric k).  The second group leaves its partial coefficients in
+// LDS; the first adds them, the centre bin, expands to the I lags through
+// the dictionary (2 Dc, -2 Ds) and keeps the first index of the maximum.
+#include "device_common.hpp"
+#include "kernels.hpp"
+
+namespace fcc {
+namespace {
+
+constexpr int kThreads = 256;
+
+template <class S, int DB, bool WRITE_Y>
+__global__ __launch_bounds__(kThreads) void pair_fold32_kernel(
+    const typename S::T* __restrict__ spec, int M, int P, int N, int I, int tau_max,
+    const uint8_t* __restrict__ pairs, const float* __restrict__ pfold /*[N/4+1][DB]*/,
+    const float* __restrict__ dict /*[I][2D]*/, int D, int32_t* __restrict__ tdoa,
+    float* __restrict__ yout) {
+  extern __shared__ float smem[];
+  const int NH = N / 2, F = NH + 1, m = N / 4;
+  float2* sp = reinterpret_cast<float2*>(smem);          // [M][F]
+  float* part = smem + 2 * M * F;                        // [128][2 DB] partial sums of the second group
+  const int64_t t = blockIdx.x;
+  const typename S::T* src = spec + t * (int64_t)M * NH;
+  for (int i = threadIdx.x; i < M * NH; i += kThreads) {
+    const int mic = i / NH, f = i - mic * NH;
+    const float2 v = spec_decode<S>(src[i]);
+    if (f == 0) {
+      sp[mic * F] = make_float2(v.x, 0.f);
+      sp[mic * F + NH] = make_float2(v.y, 0.f);
+    } else {
+      sp[mic * F + f] = v;
+    }
+  }
+  __syncthreads();
+
+  // lanes of the two halves: wavefronts [0, W/2) take bins [0, m/2), the rest [m/2, m)
+  constexpr int W = kThreads / 64;
+  const int wave = threadIdx.x >> 6;
+  const int half = __builtin_amdgcn_readfirstlane(wave >= W / 2 ? 1 : 0);   // wavefront-uniform
+  const int lane_in_half = threadIdx.x - half * (kThreads / 2);
+  const int f0 = half ? m / 2 : 0, f1 = half ? m : m / 2;
+
+  for (int pbase = 0; pbase < P; pbase += kThreads / 2) {
+    const int p = pbase + lane_in_half;
+    const bool active = p < P;
+    const int i = active ? pairs[2 * p] : 0, j = active ? pairs[2 * p + 1] : 0;
+    const float2* ei = sp + i * F;
+    const float2* ej = sp + j * F;
+    float a[DB], b[DB];
+#pragma unroll
+    for (int k = 0; k < DB; ++k) a[k] = b[k] = 0.f;
+#pragma unroll 2
+    for (int f = f0; f < f1; ++f) {
+      const float2 r1 = cmul_conj(ei[f], ej[f]);
+      const float2 r2 = cmul_conj(ei[NH - f], ej[NH - f]);
+      const float2 xs = cadd(r1, r2), xd = csub(r1, r2);
+      const float* pf = pfold + f * DB;                   // one contiguous, wavefront-uniform row
+#pragma unroll
+      for (int k = 0; k < DB; ++k) {
+        const float w = pf[k];
+        const float2 xv = (k % 2 == 0) ? xs : xd;         // eq. (6) order: k even symmetric
+        a[k] += w * xv.x;
+        b[k] += w * xv.y;
+      }
+    }
+    if (half) {
+      if (active)
+#pragma unroll
+        for (int k = 0; k < DB; ++k) {
+          part[lane_in_half * 2 * DB + 2 * k] = a[k];
+          part[lane_in_half * 2 * DB + 2 * k + 1] = b[k];
+        }
+    }
+    __syncthreads();
+    if (!half && active) {
+      const float2 rc = cmul_conj(ei[m], ej[m]);            // centre bin, symmetric k only
+#pragma unroll
+      for (int k = 0; k < DB; ++k) {
+        a[k] += part[lane_in_half * 2 * DB + 2 * k];
+        b[k] += part[lane_in_half * 2 * DB + 2 * k + 1];
+        if (k % 2 == 0) {
+          const float w = pfold[m * DB + k];
+          a[k] += w * rc.x;
+          b[k] += w * rc.y;
+        }
+      }
+      const int64_t row = t * P + p;
+      float best = 0.f;
+      int bi = 0;
+      for (int ii = 0; ii < I; ++ii) {
+        const float* dr = dict + ii * 2 * D;
+        float y = 0.f;
+#pragma unroll
+        for (int k = 0; k < DB; ++k)
+          if (k < D) y += dr[2 * k] * a[k] + dr[2 * k + 1] * b[k];
+        if (WRITE_Y) yout[row * I + ii] = y;
+        if (ii == 0 || y > best) {
+          best = y;
+          bi = ii;
+        }
+      }
+      if (!WRITE_Y) tdoa[row] = bi - tau_max;
+    }
+    __syncthreads();
+  }
+}
+
+size_t fold32_lds(int M, int N, int P, int DB) {
+  const int halfw = kThreads / 2;
+  const int pslots = P < halfw ? P : halfw;
+  return sizeof(float) * (2 * size_t(M) * (N / 2 + 1) + size_t(pslots) * 2 * DB);
+}
+
+template <class S, int DB, bool WY>
+hipError_t launch3(const PairArgs& a) {
+  auto k = pair_fold32_kernel<S, DB, WY>;
+  const size_t lds = fold32_lds(a.M, a.N, a.P, DB);
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k, dim3((unsigned)a.T), dim3(kThreads), lds, a.stream,
+                     static_cast<const typename S::T*>(a.spec), a.M, a.P, a.N, a.I, a.tau_max,
+                     a.pairs, a.pfold, a.dict, a.D, a.tdoa, a.y);
+  return hipGetLastError();
+}
+
+template <class S, int DB>
+hipError_t launch2(const PairArgs& a) {
+  return a.y ? launch3<S, DB, true>(a) : launch3<S, DB, false>(a);
+}
+
+}  // namespace
+
+bool pair_fold32_supported(const PairArgs& a) {
+  return a.method == FCC_METHOD_FCC && a.N >= 16 && a.Dfold >= a.D &&
+         (a.Dfold == 4 || a.Dfold == 8 || a.Dfold == 12 || a.Dfold == 16 || a.Dfold == 24 ||
+          a.Dfold == 32) &&
+         fold32_lds(a.M, a.N, a.P, a.Dfold) <= 160 * 1024;
+}
+
+hipError_t launch_pair_fold32(const PairArgs& a) {
+  if (a.T == 0) return hipSuccess;
+  if (!pair_fold32_supported(a)) return hipErrorInvalidValue;
+  if (a.precision != FCC_FP32) return hipErrorInvalidValue;
+  switch (a.Dfold) {
+    case 4: return launch2<SpecF32, 4>(a);
+    case 8: return launch2<SpecF32, 8>(a);
+    case 12: return launch2<SpecF32, 12>(a);
+    case 16: return launch2<SpecF32, 16>(a);
+    case 24: return launch2<SpecF32, 24>(a);
+    case 32: return launch2<SpecF32, 32>(a);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace fcc

@@ -34,7 +34,11 @@ typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef float f2 __attribute__((ext_vector_type(2)));
 
-constexpr int kYStride = 16 * 16 + 4;   // floats per lag row; the pad spreads LDS banks
+// Lag rows Y[tau][i][j] live at tau * kYStride + i * kYRow + j: rows of 17
+// and a stride of 276 words keep both the writes (lanes over j) and the
+// transposed reads (lanes over i) on distinct LDS banks.
+constexpr int kYRow = 17;
+constexpr int kYStride = 276;
 
 // Four packed complex slots as four FP16 pairs (re, im), from storage.
 template <class S> __device__ __forceinline__ uint4 load4(const typename S::T* p);
@@ -84,13 +88,17 @@ __global__ __launch_bounds__(64 * kWaves, 2) void pair_mfma_kernel(
   // wavefront holding first the frame's spectra as FP16 pairs (16 rows of
   // NH + 4 slots; rows of absent microphones are zero; the pad spreads rows
   // over the LDS banks) and, after the projection, the lag rows Y
+  // basis rows are NH + 4 words apart so the four rows a wavefront reads at
+  // once fall on different LDS banks
+  const int prow_words = NH + 4;
   uint32_t* ptab = lds_all;
-  uint32_t* slab = lds_all + Dp * NH + wave * slab_words;
+  uint32_t* slab = lds_all + Dp * prow_words + wave * slab_words;
   float* ybuf = reinterpret_cast<float*>(slab);
   const int row = NH + 4;
-  const int IB = (M + 3) >> 2;
-  for (int c = threadIdx.x; c < Dp * NH / 4; c += 64 * kWaves)
-    reinterpret_cast<uint4*>(ptab)[c] = reinterpret_cast<const uint4*>(prow16)[c];
+  for (int c = threadIdx.x; c < Dp * NH / 4; c += 64 * kWaves) {
+    const int k = c / (NH / 4), q = c - k * (NH / 4);
+    *reinterpret_cast<uint4*>(ptab + k * prow_words + 4 * q) = reinterpret_cast<const uint4*>(prow16)[c];
+  }
 
   // A operands of the expansion: G(tau = 16 tt + col, k = 4 kb + g)
   float gx[TT][KB];
@@ -151,15 +159,16 @@ __global__ __launch_bounds__(64 * kWaves, 2) void pair_mfma_kernel(
 
     const uint32_t* own = slab + col * row + 4 * g;
     const uint32_t* amic = slab + micA * row + 4 * g;
-    const uint32_t* prow = ptab + (col >> 2) * NH + 4 * g;
-    for (int s = 0; s < nsteps; ++s) {
-      const int off = 16 * s;
+    const uint32_t* prow = ptab + (col >> 2) * prow_words + 4 * g;
+    // one K step: 16 slots (32 interleaved re / im values); every tile of
+    // four microphone blocks runs (rows of absent microphones are zero)
+    auto kstep = [&](int off, bool dc_slot) {
       const h8 raw = __builtin_bit_cast(h8, *reinterpret_cast<const uint4*>(own + off));
       // B: the rotated spectrum (a - b, a + b) of microphone `col`; the packed
       // DC / Nyquist slot holds two real bins and enters unrotated.
       const h8 sw = __builtin_shufflevector(raw, raw, 1, 0, 3, 2, 5, 4, 7, 6);
       h8 B = raw + sw * sgn;
-      if (s == 0 && g == 0) {
+      if (dc_slot) {
         B[0] = raw[0];
         B[1] = raw[1];
       }
@@ -169,18 +178,19 @@ __global__ __launch_bounds__(64 * kWaves, 2) void pair_mfma_kernel(
         Am[ib] = __builtin_bit_cast(h8, *reinterpret_cast<const uint4*>(amic + 4 * ib * row + off));
 #pragma unroll
       for (int kb = 0; kb < KB; ++kb) {
-        const h8 pk = __builtin_bit_cast(h8, *reinterpret_cast<const uint4*>(prow + 4 * kb * NH + off));
+        const h8 pk = __builtin_bit_cast(h8, *reinterpret_cast<const uint4*>(prow + 4 * kb * prow_words + off));
 #pragma unroll
         for (int ib = 0; ib < 4; ++ib)
-          if (ib < IB) acc[kb][ib] = __builtin_amdgcn_mfma_f32_16x16x32_f16(Am[ib] * pk, B, acc[kb][ib], 0, 0, 0);
+          acc[kb][ib] = __builtin_amdgcn_mfma_f32_16x16x32_f16(Am[ib] * pk, B, acc[kb][ib], 0, 0, 0);
       }
-    }
+    };
+    kstep(0, g == 0);
+    for (int s = 1; s < nsteps; ++s) kstep(16 * s, false);
     wave_sync();   // every lane has read the spectra; the slab now takes Y
 
     // ---- expansion: Y_i(tau, j) = sum_k G(tau, k) H_k(i, j) --------------------
 #pragma unroll
     for (int ib = 0; ib < 4; ++ib) {
-      if (ib >= IB) continue;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int i = 4 * ib + q;
@@ -191,8 +201,10 @@ __global__ __launch_bounds__(64 * kWaves, 2) void pair_mfma_kernel(
           for (int kb = 0; kb < KB; ++kb)
             Y = __builtin_amdgcn_mfma_f32_16x16x4f32(gx[tt][kb], acc[kb][ib][q], Y, 0, 0, 0);
 #pragma unroll
-          for (int qq = 0; qq < 4; ++qq)   // rows tau >= I are padding, never read
-            ybuf[(16 * tt + 4 * g + qq) * kYStride + i * 16 + col] = Y[qq];
+          for (int qq = 0; qq < 4; ++qq) {  // rows tau >= I are padding: all go to row I, never read
+            const int tau = 16 * tt + 4 * g + qq;
+            ybuf[(tau < I ? tau : I) * kYStride + i * kYRow + col] = Y[qq];
+          }
         }
       }
     }
@@ -202,8 +214,8 @@ __global__ __launch_bounds__(64 * kWaves, 2) void pair_mfma_kernel(
     for (int p = lane; p < P; p += 64) {
       const int i = pairs[2 * p], j = pairs[2 * p + 1];
       const int64_t orow = t * P + p;
-      const float* ya = ybuf + i * 16 + j;
-      const float* yb = ybuf + (I - 1) * kYStride + j * 16 + i;
+      const float* ya = ybuf + i * kYRow + j;
+      const float* yb = ybuf + (I - 1) * kYStride + j * kYRow + i;
       float best = ya[0] + yb[0];
       int bi = 0;
       if (WRITE_Y) yout[orow * I] = best;
@@ -224,12 +236,12 @@ __global__ __launch_bounds__(64 * kWaves, 2) void pair_mfma_kernel(
 // 32-bit words of LDS one wavefront needs: the staged spectra or the lag rows
 int slab_words(const PairArgs& a) {
   const int spec_words = 16 * (a.N / 2 + 4);
-  const int y_words = ((a.I + 15) / 16) * 16 * kYStride;
+  const int y_words = (a.I + 1) * kYStride;   // I lag rows and one row taking the padding
   return spec_words > y_words ? spec_words : y_words;
 }
 
 size_t lds_bytes(const PairArgs& a, int waves) {
-  return sizeof(uint32_t) * (size_t(a.Dpad) * (a.N / 2) + size_t(waves) * slab_words(a));
+  return sizeof(uint32_t) * (size_t(a.Dpad) * (a.N / 2 + 4) + size_t(waves) * slab_words(a));
 }
 
 // wavefronts per block: four when the block's LDS fits, else two

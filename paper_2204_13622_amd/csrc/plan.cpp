@@ -350,6 +350,10 @@ fcc_status build_plan(const fcc_config& cfg, Plan& pl, std::string& err) {
   L.prow32 = off;  off = align256(off + 2 * sizeof(float) * size_t(pl.Dpad) * NH);
   L.prow16 = off;  off = align256(off + 2 * sizeof(uint16_t) * size_t(pl.Dpad) * NH);
   L.gexp = off;    off = align256(off + sizeof(float) * size_t(pl.Ipad) * pl.Dpad);
+  pl.Dfold = 0;
+  for (int c : {4, 8, 12, 16, 24, 32})
+    if (D <= c) { pl.Dfold = c; break; }
+  L.pfold = off;   off = align256(off + sizeof(float) * size_t(pl.Dfold) * (m + 1));
   L.total = off;
   pl.image.assign(L.total, 0);
   unsigned char* img = pl.image.data();
@@ -396,6 +400,8 @@ fcc_status build_plan(const fcc_config& cfg, Plan& pl, std::string& err) {
   for (int i = 0; i < I; ++i)
     for (int k = 0; k < D; ++k)
       fput(L.gexp, size_t(i) * pl.Dpad + k, pl.dc[size_t(i) * D + k] - pl.ds[size_t(i) * D + k]);
+  for (int k = 0; k < D && k < pl.Dfold; ++k)      // transposed: row f holds p_hat_k(f) for all k
+    for (int f = 0; f <= m; ++f) fput(L.pfold, size_t(f) * pl.Dfold + k, pl.p_hat[size_t(k) * (m + 1) + f]);
   for (int i = 0; i < I; ++i) {
     const double tau = double(i) / pl.r - pl.tau_max;
     for (int f = 0; f < pl.F; ++f) {

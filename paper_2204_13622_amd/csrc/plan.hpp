@@ -24,6 +24,7 @@ struct ImageLayout {
   size_t prow32 = 0;      // float2 [Dpad][N/2]
   size_t prow16 = 0;      // half2  [Dpad][N/2]
   size_t gexp = 0;        // float [Ipad][Dpad]  G(tau_i, k) = Dc - Ds; zero padded
+  size_t pfold = 0;       // float [N/4 + 1][Dfold] p_hat, transposed, for the FP32 fold kernel
   size_t total = 0;
 };
 
@@ -47,6 +48,7 @@ struct Plan {
   ImageLayout layout;
   std::vector<unsigned char> image;
   int Dpad = 0, Ipad = 0;           // D and I rounded up to the MFMA tiles (4, 16)
+  int Dfold = 0;                    // D rounded up to 4, 8, 12, 16, 24 or 32 (0 above 32)
   int spec_elem = 8;                // bytes per complex spectrum element
 };
 
