@@ -169,6 +169,23 @@ fcc_status fcc_correlation(fcc_plan plan, const void* d_basis,
                            const void* d_spec, int64_t num_frames, float* d_y,
                            hipStream_t stream);
 
+/* The projection coefficients of eq. (9) for every pair-frame,
+ * z_k = a_k + j b_k = p_hat_k . x_{s|d} (plus the centre bin for symmetric k):
+ *   d_coef [T][P][2D] FP32, (a_k, b_k) interleaved, components in the order
+ *   of fcc_basis_export (symmetric, antisymmetric, ...).
+ * The correlation is y(tau_i) = 2 sum_k (Dc(i,k) a_k - Ds(i,k) b_k).
+ * FCC method only; computed in FP32 from the spectra in any storage type. */
+fcc_status fcc_coefficients(fcc_plan plan, const void* d_basis, const void* d_spec,
+                            int64_t num_frames, float* d_coef, hipStream_t stream);
+
+/* The argmax lag refined by the quadratic interpolation of Sec. 2:
+ *   d_tau [T][P] FP32 samples, (i* - tau_max) + delta with
+ *   delta = (y(i*-1) - y(i*+1)) / (2 (y(i*-1) - 2 y(i*) + y(i*+1))),
+ *   and delta = 0 when i* is at either end of the lag window or the
+ *   denominator is 0.  FCC method only. */
+fcc_status fcc_tdoa_parabolic(fcc_plan plan, const void* d_basis, const void* d_spec,
+                              int64_t num_frames, float* d_tau, hipStream_t stream);
+
 /* Host copies of the FP64 basis (Sec. 4), for inspection and tests.  Any
  * pointer may be NULL.  Order of components: symmetric, antisymmetric,
  * symmetric, ... (eq. 6).

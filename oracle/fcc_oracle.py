@@ -45,7 +45,7 @@ __all__ = [
     "frame_signal", "stft", "mic_pairs", "cross_spectrum", "phat",
     "gcc_corr", "FccBasis", "fcc_basis", "all_singular_values", "fold",
     "fcc_coefficients", "fcc_expand", "fcc_corr", "fcc_corr_unfolded",
-    "argmax_first", "tdoa_from_corr", "parabolic_offset", "fcc_tdoa",
+    "argmax_first", "tdoa_from_corr", "parabolic_offset", "tdoa_parabolic_from_corr", "fcc_tdoa",
     "gcc_tdoa", "pipeline_spectra", "flops_gcc", "flops_direct",
     "flops_lowrank", "flops_fcc", "BasisAmbiguous",
 ]
@@ -347,6 +347,21 @@ def parabolic_offset(y_m, y_0, y_p) -> np.ndarray:
     ok = den != 0
     out[ok] = 0.5 * num[ok] / den[ok]
     return out
+
+
+def tdoa_parabolic_from_corr(y, tau_max: int, r: int = 1) -> np.ndarray:
+    """Argmax lag refined by quadratic interpolation (Sec. 2), in samples.
+    No refinement at either end of the lag window."""
+    y = np.asarray(y, dtype=np.float64)
+    i = argmax_first(y)
+    I = y.shape[-1]
+    inner = (i > 0) & (i < I - 1)
+    ic = np.clip(i, 1, I - 2)
+    ym = np.take_along_axis(y, (ic - 1)[..., None], -1)[..., 0]
+    y0 = np.take_along_axis(y, ic[..., None], -1)[..., 0]
+    yp = np.take_along_axis(y, (ic + 1)[..., None], -1)[..., 0]
+    d = np.where(inner, parabolic_offset(ym, y0, yp), 0.0)
+    return (i - r * tau_max + d) / r
 
 
 # ------------------------------------------------------------- pipelines ---

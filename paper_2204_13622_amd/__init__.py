@@ -218,6 +218,30 @@ class Plan:
                                                  _stream_handle(spec.device)))
         return out
 
+    def coefficients(self, spec, out=None):
+        """Projection coefficients of eq. (9): [T, P, 2D] float32, (a_k, b_k) interleaved."""
+        torch = _torch()
+        T = self._check_spec(spec)
+        if out is None:
+            out = torch.empty((T, self.P, 2 * self.rank), dtype=torch.float32, device=spec.device)
+        basis = self.basis_tensor(spec.device)
+        with torch.cuda.device(spec.device):
+            _lib.check(self._lib.fcc_coefficients(self._h, _ptr(basis), _ptr(spec), T, _ptr(out),
+                                                  _stream_handle(spec.device)))
+        return out
+
+    def tdoa_parabolic(self, spec, out=None):
+        """Argmax lag refined by quadratic interpolation: [T, P] float32, samples."""
+        torch = _torch()
+        T = self._check_spec(spec)
+        if out is None:
+            out = torch.empty((T, self.P), dtype=torch.float32, device=spec.device)
+        basis = self.basis_tensor(spec.device)
+        with torch.cuda.device(spec.device):
+            _lib.check(self._lib.fcc_tdoa_parabolic(self._h, _ptr(basis), _ptr(spec), T, _ptr(out),
+                                                    _stream_handle(spec.device)))
+        return out
+
     # ---- host-side inspection ------------------------------------------------
     def basis_export(self) -> dict:
         D, I, Bs = self.rank, self.I, self.N // 4 + 1

@@ -16,7 +16,8 @@ METHODS = {"fcc": 0, "gcc": 1}
 # every symbol include/fcc.h declares
 EXPORTS = ("fcc_plan_create", "fcc_plan_destroy", "fcc_plan_query", "fcc_plan_upload",
            "fcc_num_frames", "fcc_workspace_bytes", "fcc_spectra", "fcc_tdoa",
-           "fcc_tdoa_from_spectra", "fcc_correlation", "fcc_basis_export",
+           "fcc_tdoa_from_spectra", "fcc_correlation", "fcc_coefficients", "fcc_tdoa_parabolic",
+           "fcc_basis_export",
            "fcc_status_string", "fcc_last_error")
 
 
@@ -75,6 +76,8 @@ def load() -> ctypes.CDLL:
         "fcc_tdoa": [vp, vp, vp, i64, i64, vp, vp, vp],
         "fcc_tdoa_from_spectra": [vp, vp, vp, i64, vp, vp],
         "fcc_correlation": [vp, vp, vp, i64, vp, vp],
+        "fcc_coefficients": [vp, vp, vp, i64, vp, vp],
+        "fcc_tdoa_parabolic": [vp, vp, vp, i64, vp, vp],
         "fcc_basis_export": [vp, dp, i32p, dp, dp, dp],
     }
     for name, args in sig.items():

@@ -191,21 +191,29 @@ fcc_status fcc_spectra(fcc_plan plan, const void* d_basis, const float* d_x, int
 }
 
 static fcc_status pair_stage(const fcc::Plan& p, const void* d_basis, const void* d_spec, int64_t T,
-                             int32_t* d_tdoa, float* d_y, hipStream_t stream) {
+                             int32_t* d_tdoa, float* d_y, hipStream_t stream, float* d_coef = nullptr,
+                             float* d_tau = nullptr) {
   if (T < 0) return set_error(FCC_ERR_INVALID_ARG, "num_frames must be >= 0");
   fcc_status st = check_basis(d_basis);
   if (st != FCC_OK) return st;
   if (T == 0) return FCC_OK;
   if ((st = check_spec(p, d_spec)) != FCC_OK) return st;
-  if (!d_tdoa && !d_y) return set_error(FCC_ERR_INVALID_ARG, "output pointer is NULL");
-  if (d_tdoa && !aligned(d_tdoa, 4)) return set_error(FCC_ERR_INVALID_ARG, "d_tdoa misaligned");
-  if (d_y && !aligned(d_y, 4)) return set_error(FCC_ERR_INVALID_ARG, "d_y misaligned");
+  if (!d_tdoa && !d_y && !d_coef && !d_tau) return set_error(FCC_ERR_INVALID_ARG, "output pointer is NULL");
+  for (const void* o : {static_cast<const void*>(d_tdoa), static_cast<const void*>(d_y),
+                        static_cast<const void*>(d_coef), static_cast<const void*>(d_tau)})
+    if (o && !aligned(o, 4)) return set_error(FCC_ERR_INVALID_ARG, "output pointer misaligned");
   if (T > int64_t(INT32_MAX)) return set_error(FCC_ERR_UNSUPPORTED, "too many frames for one call");
   fcc::PairArgs a = pair_args(p, d_basis, d_spec, T, stream);
   a.tdoa = d_tdoa;
   a.y = d_y;
+  a.coef = d_coef;
+  a.tau_frac = d_tau;
   hipError_t e;
-  if (fcc::pair_mfma_supported(a)) e = fcc::launch_pair_mfma(a);
+  if (d_coef || d_tau) {
+    if (p.method != FCC_METHOD_FCC) return set_error(FCC_ERR_UNSUPPORTED, "coefficients and interpolation need the FCC method");
+    if (!fcc::pair_fold32_supported(a)) return set_error(FCC_ERR_UNSUPPORTED, "shape outside the fold kernel's limits");
+    e = fcc::launch_pair_fold32(a);
+  } else if (fcc::pair_mfma_supported(a)) e = fcc::launch_pair_mfma(a);
   else if (p.precision == FCC_FP32 && fcc::pair_fold32_supported(a)) e = fcc::launch_pair_fold32(a);
   else e = fcc::launch_pair_valu(a);
   if (e == hipErrorInvalidValue)
@@ -225,6 +233,20 @@ fcc_status fcc_correlation(fcc_plan plan, const void* d_basis, const void* d_spe
   if (!plan) return set_error(FCC_ERR_INVALID_ARG, "NULL plan");
   if (num_frames > 0 && !d_y) return set_error(FCC_ERR_INVALID_ARG, "d_y is NULL");
   return pair_stage(plan->p, d_basis, d_spec, num_frames, nullptr, d_y, stream);
+}
+
+fcc_status fcc_coefficients(fcc_plan plan, const void* d_basis, const void* d_spec, int64_t num_frames,
+                            float* d_coef, hipStream_t stream) {
+  if (!plan) return set_error(FCC_ERR_INVALID_ARG, "NULL plan");
+  if (num_frames > 0 && !d_coef) return set_error(FCC_ERR_INVALID_ARG, "d_coef is NULL");
+  return pair_stage(plan->p, d_basis, d_spec, num_frames, nullptr, nullptr, stream, d_coef, nullptr);
+}
+
+fcc_status fcc_tdoa_parabolic(fcc_plan plan, const void* d_basis, const void* d_spec, int64_t num_frames,
+                              float* d_tau, hipStream_t stream) {
+  if (!plan) return set_error(FCC_ERR_INVALID_ARG, "NULL plan");
+  if (num_frames > 0 && !d_tau) return set_error(FCC_ERR_INVALID_ARG, "d_tau is NULL");
+  return pair_stage(plan->p, d_basis, d_spec, num_frames, nullptr, nullptr, stream, nullptr, d_tau);
 }
 
 fcc_status fcc_tdoa(fcc_plan plan, const void* d_basis, const float* d_x, int64_t num_samples, int64_t ld,

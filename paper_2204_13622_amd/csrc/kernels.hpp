@@ -37,6 +37,8 @@ struct PairArgs {
   const float* pfold;        // [N/4 + 1][Dfold] p_hat transposed, zero beyond D
   int32_t* tdoa;             // [T][P] or null
   float* y;                  // [T][P][I] or null
+  float* coef;               // [T][P][2D] projection coefficients (a_k, b_k), or null
+  float* tau_frac;           // [T][P] argmax refined by quadratic interpolation, or null
   hipStream_t stream;
 };
 

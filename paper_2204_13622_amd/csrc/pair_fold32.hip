@@ -10,8 +10,14 @@
 //   R(f) = e_i(f) e_j(f)^*,  R(N/2 - f),  x_s = R(f) + R(N/2 - f),  x_d = R(f) - R(N/2 - f)
 // and accumulates z_k += p_hat_k(f) x_s (symmetric k) or p_hat_k(f) x_d
 // (antisymmetric k).  The second group leaves its partial coefficients in
-// LDS; the first adds them, the centre bin, expands to the I lags through
-// the dictionary (2 Dc, -2 Ds) and keeps the first index of the maximum.
+// LDS; the first adds them and the centre bin.  Outputs, by mode: the
+// coefficients (a_k, b_k) themselves; or the expansion to the I lags through
+// the dictionary (2 Dc, -2 Ds) followed by the first-index argmax, written as
+// the integer lag, as the lag refined by quadratic interpolation around the
+// maximum (Sec. 2), or as the correlation y itself.
+//
+// Storage types other than FP32 are decoded to FP32 while staging, so every
+// precision can produce coefficients and interpolated lags.
 #include "device_common.hpp"
 #include "kernels.hpp"
 
@@ -19,13 +25,14 @@ namespace fcc {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int kOutLag = 0, kOutCorr = 1, kOutCoef = 2, kOutParabolic = 3;
 
-template <class S, int DB, bool WRITE_Y>
+template <class S, int DB, int OUT>
 __global__ __launch_bounds__(kThreads) void pair_fold32_kernel(
     const typename S::T* __restrict__ spec, int M, int P, int N, int I, int tau_max,
     const uint8_t* __restrict__ pairs, const float* __restrict__ pfold /*[N/4+1][DB]*/,
     const float* __restrict__ dict /*[I][2D]*/, int D, int32_t* __restrict__ tdoa,
-    float* __restrict__ yout) {
+    float* __restrict__ fout) {
   extern __shared__ float smem[];
   const int NH = N / 2, F = NH + 1, m = N / 4;
   float2* sp = reinterpret_cast<float2*>(smem);          // [M][F]
@@ -96,21 +103,39 @@ __global__ __launch_bounds__(kThreads) void pair_fold32_kernel(
         }
       }
       const int64_t row = t * P + p;
-      float best = 0.f;
-      int bi = 0;
-      for (int ii = 0; ii < I; ++ii) {
-        const float* dr = dict + ii * 2 * D;
-        float y = 0.f;
+      if (OUT == kOutCoef) {
+        for (int k = 0; k < D && k < DB; ++k) {
+          fout[row * 2 * D + 2 * k] = a[k];
+          fout[row * 2 * D + 2 * k + 1] = b[k];
+        }
+      } else {
+        float best = 0.f, prev = 0.f, y_lo = 0.f, y_hi = 0.f;
+        int bi = 0;
+        for (int ii = 0; ii < I; ++ii) {
+          const float* dr = dict + ii * 2 * D;
+          float y = 0.f;
 #pragma unroll
-        for (int k = 0; k < DB; ++k)
-          if (k < D) y += dr[2 * k] * a[k] + dr[2 * k + 1] * b[k];
-        if (WRITE_Y) yout[row * I + ii] = y;
-        if (ii == 0 || y > best) {
-          best = y;
-          bi = ii;
+          for (int k = 0; k < DB; ++k)
+            if (k < D) y += dr[2 * k] * a[k] + dr[2 * k + 1] * b[k];
+          if (OUT == kOutCorr) fout[row * I + ii] = y;
+          if (ii == 0 || y > best) {
+            best = y;
+            bi = ii;
+            y_lo = prev;
+          }
+          if (ii == bi + 1) y_hi = y;
+          prev = y;
+        }
+        if (OUT == kOutLag) tdoa[row] = bi - tau_max;
+        if (OUT == kOutParabolic) {
+          // vertex of the parabola through (-1, y_lo), (0, best), (1, y_hi);
+          // no refinement at the window edges or on a flat top
+          float d = 0.f;
+          const float den = y_lo - 2.f * best + y_hi;
+          if (bi > 0 && bi < I - 1 && den != 0.f) d = 0.5f * (y_lo - y_hi) / den;
+          fout[row] = (float)(bi - tau_max) + d;
         }
       }
-      if (!WRITE_Y) tdoa[row] = bi - tau_max;
     }
     __syncthreads();
   }
@@ -122,24 +147,41 @@ size_t fold32_lds(int M, int N, int P, int DB) {
   return sizeof(float) * (2 * size_t(M) * (N / 2 + 1) + size_t(pslots) * 2 * DB);
 }
 
-template <class S, int DB, bool WY>
+template <class S, int DB, int OUT>
 hipError_t launch3(const PairArgs& a) {
-  auto k = pair_fold32_kernel<S, DB, WY>;
+  auto k = pair_fold32_kernel<S, DB, OUT>;
   const size_t lds = fold32_lds(a.M, a.N, a.P, DB);
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
+  float* fout = OUT == kOutCorr ? a.y : (OUT == kOutCoef ? a.coef : a.tau_frac);
   hipLaunchKernelGGL(k, dim3((unsigned)a.T), dim3(kThreads), lds, a.stream,
                      static_cast<const typename S::T*>(a.spec), a.M, a.P, a.N, a.I, a.tau_max,
-                     a.pairs, a.pfold, a.dict, a.D, a.tdoa, a.y);
+                     a.pairs, a.pfold, a.dict, a.D, a.tdoa, fout);
   return hipGetLastError();
 }
 
 template <class S, int DB>
 hipError_t launch2(const PairArgs& a) {
-  return a.y ? launch3<S, DB, true>(a) : launch3<S, DB, false>(a);
+  if (a.coef) return launch3<S, DB, kOutCoef>(a);
+  if (a.tau_frac) return launch3<S, DB, kOutParabolic>(a);
+  if (a.y) return launch3<S, DB, kOutCorr>(a);
+  return launch3<S, DB, kOutLag>(a);
+}
+
+template <class S>
+hipError_t launch1(const PairArgs& a) {
+  switch (a.Dfold) {
+    case 4: return launch2<S, 4>(a);
+    case 8: return launch2<S, 8>(a);
+    case 12: return launch2<S, 12>(a);
+    case 16: return launch2<S, 16>(a);
+    case 24: return launch2<S, 24>(a);
+    case 32: return launch2<S, 32>(a);
+  }
+  return hipErrorInvalidValue;
 }
 
 }  // namespace
@@ -154,14 +196,11 @@ bool pair_fold32_supported(const PairArgs& a) {
 hipError_t launch_pair_fold32(const PairArgs& a) {
   if (a.T == 0) return hipSuccess;
   if (!pair_fold32_supported(a)) return hipErrorInvalidValue;
-  if (a.precision != FCC_FP32) return hipErrorInvalidValue;
-  switch (a.Dfold) {
-    case 4: return launch2<SpecF32, 4>(a);
-    case 8: return launch2<SpecF32, 8>(a);
-    case 12: return launch2<SpecF32, 12>(a);
-    case 16: return launch2<SpecF32, 16>(a);
-    case 24: return launch2<SpecF32, 24>(a);
-    case 32: return launch2<SpecF32, 32>(a);
+  switch (a.precision) {
+    case FCC_FP32: return launch1<SpecF32>(a);
+    case FCC_BF16: return launch1<SpecBF16>(a);
+    case FCC_FP16: return launch1<SpecF16>(a);
+    case FCC_FP8_E4M3: return launch1<SpecE4M3>(a);
   }
   return hipErrorInvalidValue;
 }
