@@ -214,3 +214,47 @@ def random_signals(seed: int, M: int, L: int, kind: str = "white") -> np.ndarray
     if kind == "gated":
         x[:, L // 3: L // 3 + L // 4] = 0.0
     return x.astype(np.float32)
+
+
+def fractional_delay_frames(seed: int, count: int, M: int = 8, radius: float = 0.04,
+                            fs: float = 16000.0, N: int = 512, c: float = 343.0,
+                            snr_db=(0.0, 20.0), chunk: int = 2048):
+    """`count` independent single-frame recordings of a circular array with
+    fractional (sub-sample) propagation delays.
+
+    Each frame has its own far-field direction, uniform on the sphere, so the
+    delay of every mic pair is uniform over that pair's physical range
+    [-d_ij fs / c, d_ij fs / c].  The source is white and band-limited with
+    period 2N; it is delayed in the frequency domain, which is exact
+    band-limited (periodic sinc) interpolation, and the middle N samples are
+    kept.  Each mic gets white sensor noise at an SNR uniform in `snr_db`
+    relative to its own frame power.
+
+    Returns (x, delays, xyz): x [M][count * N] float32, frame e occupying
+    samples [e N, (e + 1) N) (frame with hop N); delays [count][M] in samples
+    (the arrival time at each mic relative to the array centre); xyz [M][3].
+    """
+    rng = np.random.default_rng(seed)
+    xyz = circular_array(M, radius)
+    Lp = 2 * N
+    f = np.arange(Lp // 2 + 1)
+    x = np.empty((M, count * N), dtype=np.float32)
+    delays = np.empty((count, M))
+    for e0 in range(0, count, chunk):
+        E = min(chunk, count - e0)
+        z = rng.uniform(-1.0, 1.0, E)
+        phi = rng.uniform(0.0, 2.0 * np.pi, E)
+        rho = np.sqrt(1.0 - z * z)
+        u = np.stack([rho * np.cos(phi), rho * np.sin(phi), z], axis=1)      # [E][3]
+        d = -(u @ xyz.T) * fs / c                                           # [E][M]
+        S = rng.standard_normal((E, f.size)) + 1j * rng.standard_normal((E, f.size))
+        S[:, 0] = S[:, 0].real
+        S[:, -1] = 0.0
+        phase = np.exp(-2j * np.pi * f[None, None, :] * d[:, :, None] / Lp)  # [E][M][F]
+        sig = np.fft.irfft(S[:, None, :] * phase, n=Lp, axis=-1)[:, :, N // 2: N // 2 + N]
+        p = np.mean(sig * sig, axis=-1, keepdims=True)
+        snr = rng.uniform(snr_db[0], snr_db[1], (E, M, 1))
+        sig = sig + rng.standard_normal(sig.shape) * np.sqrt(p * 10.0 ** (-snr / 10.0))
+        x[:, e0 * N:(e0 + E) * N] = sig.transpose(1, 0, 2).reshape(M, E * N)
+        delays[e0:e0 + E] = d
+    return x, delays, xyz

@@ -194,6 +194,51 @@ fcc_status fcc_tdoa_parabolic(fcc_plan plan, const void* d_basis, const void* d_
 fcc_status fcc_basis_export(fcc_plan plan, double* sigma, int32_t* is_sym,
                             double* p_hat, double* dc, double* ds);
 
+/* ---- learned sub-sample TDoA ------------------------------------------------
+ * Not from the paper: a multilayer perceptron refining the FCC lag of one
+ * pair-frame from its projection coefficients (fcc_coefficients).  One row =
+ * one pair-frame, c = (a_1, b_1, ..., a_D, b_D), in_dim = 2D.
+ *   u = c / ||c||_2,  h1 = gelu(u W1 + b1),  h2 = gelu(h1 W2 + b2),
+ *   (mu, s) = h2 W3 + b3,  s clipped to [-8, 8]
+ * mu is the TDoA in samples, s the log-variance of a Gaussian error model
+ * (confidence exp(-s/2)); gelu is the tanh form.  Matrix products run on FP16
+ * matrix cores with FP32 accumulation; everything else is FP32.
+ * Parameters: one FP32 vector, W1 [in_dim][hidden], b1 [hidden],
+ * W2 [hidden][hidden], b2 [hidden], W3 [hidden][2], b3 [2], row-major.
+ * in_dim in [1, 64], hidden a multiple of 16 in [16, 512]; rows < 2^31.
+ * Workspace: fcc_mlp_workspace_bytes, caller-owned. */
+size_t fcc_mlp_num_params(int32_t in_dim, int32_t hidden);
+fcc_status fcc_mlp_workspace_bytes(int32_t in_dim, int32_t hidden, int64_t rows, size_t* bytes);
+
+/* d_coef [rows][in_dim] -> d_out [rows][2] = (mu, s). */
+fcc_status fcc_mlp_forward(const float* d_params, int32_t in_dim, int32_t hidden, const float* d_coef,
+                           int64_t rows, float* d_out, void* d_workspace, hipStream_t stream);
+
+/* Forward plus the gradient of the mean Gaussian negative log-likelihood
+ * L = (1/rows) sum 0.5 (exp(-s) (mu - target)^2 + s) into d_grad (parameter
+ * layout, overwritten); the summed (not averaged) loss is ADDED to
+ * *d_loss_sum (one FP32 on the device); d_out receives (mu, s). */
+fcc_status fcc_mlp_backward(const float* d_params, int32_t in_dim, int32_t hidden, const float* d_coef,
+                            const float* d_target, int64_t rows, float* d_grad, float* d_loss_sum,
+                            float* d_out, void* d_workspace, hipStream_t stream);
+
+/* One Adam update (bias-corrected, step >= 1) of n parameters in place. */
+fcc_status fcc_mlp_adam(float* d_params, float* d_m, float* d_v, const float* d_grad, int64_t n, float lr,
+                        float beta1, float beta2, float eps, int32_t step, hipStream_t stream);
+
+/* The learned estimate for every pair-frame of a plan, in one call:
+ * coefficients (fcc_coefficients) -> MLP (in_dim = 2 * rank) -> (mu, s);
+ * d_tau [T][P] FP32 samples is mu where the confidence exp(-s/2) is at least
+ * min_confidence, and the interpolated FCC lag (fcc_tdoa_parabolic)
+ * elsewhere; d_confidence [T][P] (may be NULL) receives exp(-s/2).
+ * min_confidence = +inf gives plain FCC with interpolation, 0 the MLP alone.
+ * Workspace: fcc_learned_workspace_bytes, caller-owned, 256-byte aligned.
+ * FCC method only. */
+fcc_status fcc_learned_workspace_bytes(fcc_plan plan, int32_t hidden, int64_t num_frames, size_t* bytes);
+fcc_status fcc_tdoa_learned(fcc_plan plan, const void* d_basis, const void* d_spec, int64_t num_frames,
+                            const float* d_params, int32_t hidden, float min_confidence, float* d_tau,
+                            float* d_confidence, void* d_workspace, hipStream_t stream);
+
 const char* fcc_status_string(fcc_status status);
 const char* fcc_last_error(void);
 

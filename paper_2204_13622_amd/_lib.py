@@ -17,7 +17,8 @@ METHODS = {"fcc": 0, "gcc": 1}
 EXPORTS = ("fcc_plan_create", "fcc_plan_destroy", "fcc_plan_query", "fcc_plan_upload",
            "fcc_num_frames", "fcc_workspace_bytes", "fcc_spectra", "fcc_tdoa",
            "fcc_tdoa_from_spectra", "fcc_correlation", "fcc_coefficients", "fcc_tdoa_parabolic",
-           "fcc_basis_export",
+           "fcc_basis_export", "fcc_mlp_num_params", "fcc_mlp_workspace_bytes", "fcc_mlp_forward",
+           "fcc_mlp_backward", "fcc_mlp_adam", "fcc_learned_workspace_bytes", "fcc_tdoa_learned",
            "fcc_status_string", "fcc_last_error")
 
 
@@ -79,11 +80,20 @@ def load() -> ctypes.CDLL:
         "fcc_coefficients": [vp, vp, vp, i64, vp, vp],
         "fcc_tdoa_parabolic": [vp, vp, vp, i64, vp, vp],
         "fcc_basis_export": [vp, dp, i32p, dp, dp, dp],
+        "fcc_mlp_workspace_bytes": [ctypes.c_int32, ctypes.c_int32, i64, ctypes.POINTER(ctypes.c_size_t)],
+        "fcc_mlp_forward": [vp, ctypes.c_int32, ctypes.c_int32, vp, i64, vp, vp, vp],
+        "fcc_mlp_backward": [vp, ctypes.c_int32, ctypes.c_int32, vp, vp, i64, vp, vp, vp, vp, vp],
+        "fcc_learned_workspace_bytes": [vp, ctypes.c_int32, i64, ctypes.POINTER(ctypes.c_size_t)],
+        "fcc_tdoa_learned": [vp, vp, vp, i64, vp, ctypes.c_int32, ctypes.c_float, vp, vp, vp, vp],
+        "fcc_mlp_adam": [vp, vp, vp, vp, i64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                         ctypes.c_float, ctypes.c_int32, vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = ctypes.c_int
+    lib.fcc_mlp_num_params.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    lib.fcc_mlp_num_params.restype = ctypes.c_size_t
     lib.fcc_plan_destroy.argtypes = [vp]
     lib.fcc_plan_destroy.restype = None
     lib.fcc_status_string.argtypes = [ctypes.c_int]

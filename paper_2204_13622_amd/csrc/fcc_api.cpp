@@ -277,6 +277,115 @@ fcc_status fcc_basis_export(fcc_plan plan, double* sigma, int32_t* is_sym, doubl
   return FCC_OK;
 }
 
+static fcc_status check_mlp_shape(int32_t in_dim, int32_t hidden, int64_t rows) {
+  if (in_dim < 1 || in_dim > 64) return set_error(FCC_ERR_INVALID_ARG, "in_dim must be in [1, 64]");
+  if (hidden < 16 || hidden > 512 || hidden % 16) return set_error(FCC_ERR_INVALID_ARG, "hidden must be a multiple of 16 in [16, 512]");
+  if (rows < 0 || rows >= (int64_t(1) << 31)) return set_error(FCC_ERR_INVALID_ARG, "rows must be in [0, 2^31)");
+  return FCC_OK;
+}
+
+size_t fcc_mlp_num_params(int32_t in_dim, int32_t hidden) {
+  if (in_dim < 1 || hidden < 1) return 0;
+  return fcc::mlp_num_params(in_dim, hidden);
+}
+
+fcc_status fcc_mlp_workspace_bytes(int32_t in_dim, int32_t hidden, int64_t rows, size_t* bytes) {
+  if (!bytes) return set_error(FCC_ERR_INVALID_ARG, "NULL argument");
+  fcc_status st = check_mlp_shape(in_dim, hidden, rows);
+  if (st != FCC_OK) return st;
+  *bytes = sizeof(float) * fcc::mlp_workspace_floats(in_dim, hidden, rows);
+  return FCC_OK;
+}
+
+fcc_status fcc_mlp_forward(const float* d_params, int32_t in_dim, int32_t hidden, const float* d_coef,
+                           int64_t rows, float* d_out, void* d_workspace, hipStream_t stream) {
+  fcc_status st = check_mlp_shape(in_dim, hidden, rows);
+  if (st != FCC_OK) return st;
+  if (rows == 0) return FCC_OK;
+  if (!d_params || !d_coef || !d_out || !d_workspace) return set_error(FCC_ERR_INVALID_ARG, "NULL pointer");
+  return hip_status(fcc::mlp_forward(d_params, in_dim, hidden, d_coef, rows, d_out, d_workspace, stream),
+                    "mlp forward launch");
+}
+
+fcc_status fcc_mlp_backward(const float* d_params, int32_t in_dim, int32_t hidden, const float* d_coef,
+                            const float* d_target, int64_t rows, float* d_grad, float* d_loss_sum,
+                            float* d_out, void* d_workspace, hipStream_t stream) {
+  fcc_status st = check_mlp_shape(in_dim, hidden, rows);
+  if (st != FCC_OK) return st;
+  if (rows == 0) return FCC_OK;
+  if (!d_params || !d_coef || !d_target || !d_grad || !d_loss_sum || !d_out || !d_workspace)
+    return set_error(FCC_ERR_INVALID_ARG, "NULL pointer");
+  return hip_status(fcc::mlp_backward(d_params, in_dim, hidden, d_coef, d_target, rows, d_grad, d_loss_sum,
+                                      d_out, d_workspace, stream),
+                    "mlp backward launch");
+}
+
+fcc_status fcc_mlp_adam(float* d_params, float* d_m, float* d_v, const float* d_grad, int64_t n, float lr,
+                        float beta1, float beta2, float eps, int32_t step, hipStream_t stream) {
+  if (n < 0 || step < 1) return set_error(FCC_ERR_INVALID_ARG, "n must be >= 0 and step >= 1");
+  if (n == 0) return FCC_OK;
+  if (!d_params || !d_m || !d_v || !d_grad) return set_error(FCC_ERR_INVALID_ARG, "NULL pointer");
+  return hip_status(fcc::mlp_adam(d_params, d_m, d_v, d_grad, n, lr, beta1, beta2, eps, step, stream),
+                    "adam launch");
+}
+
+namespace {
+// learned-path workspace: coefficients, fallback lags, MLP output, MLP scratch
+struct LearnedCarve {
+  size_t coef, fallback, out, mlp, total;
+};
+size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
+LearnedCarve learned_carve(const fcc::Plan& p, int hidden, int64_t T) {
+  const int64_t R = T * p.P;
+  LearnedCarve c{};
+  c.coef = 0;
+  c.fallback = c.coef + round256(sizeof(float) * size_t(R) * 2 * p.D);
+  c.out = c.fallback + round256(sizeof(float) * size_t(R));
+  c.mlp = c.out + round256(sizeof(float) * size_t(R) * 2);
+  c.total = c.mlp + round256(sizeof(float) * fcc::mlp_workspace_floats(2 * p.D, hidden, R));
+  return c;
+}
+}  // namespace
+
+fcc_status fcc_learned_workspace_bytes(fcc_plan plan, int32_t hidden, int64_t num_frames, size_t* bytes) {
+  if (!plan || !bytes) return set_error(FCC_ERR_INVALID_ARG, "NULL argument");
+  if (num_frames < 0) return set_error(FCC_ERR_INVALID_ARG, "num_frames must be >= 0");
+  fcc_status st = check_mlp_shape(2 * plan->p.D, hidden, num_frames * plan->p.P);
+  if (st != FCC_OK) return st;
+  *bytes = learned_carve(plan->p, hidden, num_frames).total;
+  return FCC_OK;
+}
+
+fcc_status fcc_tdoa_learned(fcc_plan plan, const void* d_basis, const void* d_spec, int64_t num_frames,
+                            const float* d_params, int32_t hidden, float min_confidence, float* d_tau,
+                            float* d_confidence, void* d_workspace, hipStream_t stream) {
+  if (!plan) return set_error(FCC_ERR_INVALID_ARG, "NULL plan");
+  const fcc::Plan& p = plan->p;
+  if (num_frames < 0) return set_error(FCC_ERR_INVALID_ARG, "num_frames must be >= 0");
+  if (p.method != FCC_METHOD_FCC) return set_error(FCC_ERR_UNSUPPORTED, "the learned stage needs the FCC method");
+  const int64_t R = num_frames * p.P;
+  fcc_status st = check_mlp_shape(2 * p.D, hidden, R);
+  if (st != FCC_OK) return st;
+  if (num_frames == 0) return FCC_OK;
+  if (!d_params || !d_tau || !d_workspace) return set_error(FCC_ERR_INVALID_ARG, "NULL pointer");
+  if (!aligned(d_workspace, 256)) return set_error(FCC_ERR_INVALID_ARG, "d_workspace must be 256-byte aligned");
+  if (!aligned(d_tau, 4) || !aligned(d_params, 4) || (d_confidence && !aligned(d_confidence, 4)))
+    return set_error(FCC_ERR_INVALID_ARG, "pointer misaligned");
+  const LearnedCarve c = learned_carve(p, hidden, num_frames);
+  char* ws = static_cast<char*>(d_workspace);
+  float* coef = reinterpret_cast<float*>(ws + c.coef);
+  float* fallback = reinterpret_cast<float*>(ws + c.fallback);
+  float* out = reinterpret_cast<float*>(ws + c.out);
+  if ((st = pair_stage(p, d_basis, d_spec, num_frames, nullptr, nullptr, stream, coef)) != FCC_OK) return st;
+  if ((st = pair_stage(p, d_basis, d_spec, num_frames, nullptr, nullptr, stream, nullptr, fallback)) != FCC_OK)
+    return st;
+  if ((st = hip_status(fcc::mlp_forward(d_params, 2 * p.D, hidden, coef, R, out, ws + c.mlp, stream),
+                       "mlp forward launch")) != FCC_OK)
+    return st;
+  return hip_status(fcc::mlp_select(out, fallback, R, min_confidence, d_tau, d_confidence, stream),
+                    "select launch");
+}
+
 const char* fcc_status_string(fcc_status status) {
   switch (status) {
     case FCC_OK: return "FCC_OK";

@@ -43,6 +43,17 @@ struct PairArgs {
 };
 
 hipError_t launch_stft_phat(const StftArgs& a);
+
+size_t mlp_num_params(int in_dim, int hidden);
+size_t mlp_workspace_floats(int in_dim, int hidden, int64_t rows);
+hipError_t mlp_forward(const float* theta, int in_dim, int hidden, const float* x, int64_t rows, float* out,
+                       void* ws, hipStream_t st);
+hipError_t mlp_backward(const float* theta, int in_dim, int hidden, const float* x, const float* delta,
+                        int64_t rows, float* grad, float* loss_sum, float* out, void* ws, hipStream_t st);
+hipError_t mlp_select(const float* out, const float* fallback, int64_t rows, float min_conf, float* tau,
+                      float* conf, hipStream_t st);
+hipError_t mlp_adam(float* theta, float* m, float* v, const float* grad, int64_t n, float lr, float b1, float b2,
+                    float eps, int step, hipStream_t st);
 hipError_t launch_pair_valu(const PairArgs& a);
 bool pair_mfma_supported(const PairArgs& a);
 bool pair_fold32_supported(const PairArgs& a);

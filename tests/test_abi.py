@@ -125,3 +125,25 @@ def test_host_basis_matches_oracle(fcc, xyz, fs, N, D):
             assert e["p_hat"][k, m] == 0.0
     assert np.array_equal(e["Dc"], e["Dc"][::-1])
     assert np.array_equal(e["Ds"], -e["Ds"][::-1])
+
+
+def test_mlp_host_queries(fcc):
+    import oracle.mlp_oracle as MO
+    from paper_2204_13622_amd.learned import learned_workspace_bytes
+    lib = fcc._lib.load()
+    for in_dim, H in [(10, 128), (22, 128), (64, 512), (1, 16)]:
+        assert lib.fcc_mlp_num_params(in_dim, H) == MO.num_params(in_dim, H)
+    b = ctypes.c_size_t()
+    assert lib.fcc_mlp_workspace_bytes(10, 128, 1000, ctypes.byref(b)) == 0
+    assert b.value == 4 * 1000 * (10 + 6 * 128 + 4)
+    for bad in [(0, 128, 10), (65, 128, 10), (10, 40, 10), (10, 528, 10), (10, 128, -1)]:
+        assert lib.fcc_mlp_workspace_bytes(*bad, ctypes.byref(b)) == -1, bad
+    # argument errors return before any device work
+    assert lib.fcc_mlp_forward(None, 10, 128, None, 5, None, None, None) == -1
+    assert lib.fcc_mlp_adam(None, None, None, None, 5, 1e-3, 0.9, 0.999, 1e-8, 0, None) == -1
+    p = fcc.Plan(circular_array(8, 0.04), 16000.0, frame_size=512, hop=512, rank=5)
+    R = 100 * p.P
+    assert learned_workspace_bytes(p, 128, 100) >= 4 * R * (10 + 1 + 2) + 4 * R * (10 + 6 * 128 + 4)
+    assert learned_workspace_bytes(p, 128, 100) % 256 == 0
+    with pytest.raises(fcc.FccError):
+        learned_workspace_bytes(p, 100, 10)
