@@ -75,6 +75,7 @@ fcc::PairArgs pair_args(const fcc::Plan& p, const void* d_basis, const void* d_s
   a.gexp = reinterpret_cast<const float*>(image_ptr(d_basis, p.layout.gexp));
   a.Dfold = p.Dfold;
   a.pfold = reinterpret_cast<const float*>(image_ptr(d_basis, p.layout.pfold));
+  a.twiddle = reinterpret_cast<const float2*>(image_ptr(d_basis, p.layout.twiddle));
   a.stream = stream;
   return a;
 }
@@ -213,7 +214,8 @@ static fcc_status pair_stage(const fcc::Plan& p, const void* d_basis, const void
     if (p.method != FCC_METHOD_FCC) return set_error(FCC_ERR_UNSUPPORTED, "coefficients and interpolation need the FCC method");
     if (!fcc::pair_fold32_supported(a)) return set_error(FCC_ERR_UNSUPPORTED, "shape outside the fold kernel's limits");
     e = fcc::launch_pair_fold32(a);
-  } else if (fcc::pair_mfma_supported(a)) e = fcc::launch_pair_mfma(a);
+  } else if (fcc::gcc_ifft_supported(a)) e = fcc::launch_gcc_ifft(a);
+  else if (fcc::pair_mfma_supported(a)) e = fcc::launch_pair_mfma(a);
   else if (p.precision == FCC_FP32 && fcc::pair_fold32_supported(a)) e = fcc::launch_pair_fold32(a);
   else e = fcc::launch_pair_valu(a);
   if (e == hipErrorInvalidValue)

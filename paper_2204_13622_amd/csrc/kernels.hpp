@@ -35,6 +35,7 @@ struct PairArgs {
   const float* gexp;         // [Ipad][Dpad] G = Dc - Ds
   int Dfold;                 // D padded to the FP32 fold kernel's register block
   const float* pfold;        // [N/4 + 1][Dfold] p_hat transposed, zero beyond D
+  const float2* twiddle;     // [N] exp(-j 2 pi n / N)
   int32_t* tdoa;             // [T][P] or null
   float* y;                  // [T][P][I] or null
   float* coef;               // [T][P][2D] projection coefficients (a_k, b_k), or null
@@ -58,6 +59,8 @@ hipError_t launch_pair_valu(const PairArgs& a);
 bool pair_mfma_supported(const PairArgs& a);
 bool pair_fold32_supported(const PairArgs& a);
 hipError_t launch_pair_fold32(const PairArgs& a);
+bool gcc_ifft_supported(const PairArgs& a);
+hipError_t launch_gcc_ifft(const PairArgs& a);
 hipError_t launch_pair_mfma(const PairArgs& a);
 
 }  // namespace fcc

@@ -158,7 +158,7 @@ size_t pair_valu_lds_bytes(int M, int N, int D) {
 
 hipError_t launch_pair_valu(const PairArgs& a) {
   if (a.T == 0) return hipSuccess;
-  const size_t lds = pair_valu_lds_bytes(a.M, a.N, a.D);
+  const size_t lds = pair_valu_lds_bytes(a.M, a.N, a.method == FCC_METHOD_GCC ? 0 : a.D);   // GCC stages no basis
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   switch (a.precision) {
     case FCC_FP32: return launch2<SpecF32>(a, lds);

@@ -105,7 +105,7 @@ def test_pair_stage_from_oracle_spectra(torch, fcc, config, seconds, D):
     _check_fp32(t.cpu().numpy(), y.cpu().numpy(), y_ref, p.tau_max)
 
 
-@pytest.mark.parametrize("config,seconds", [(1, 1.0), (2, 1.0)])
+@pytest.mark.parametrize("config,seconds", [(1, 1.0), (2, 1.0), (3, 0.5)])
 def test_gcc_method(torch, fcc, config, seconds):
     _say(f"GCC method fp32 config {config}")
     rec = make_recording(config, seconds=seconds)
@@ -117,6 +117,37 @@ def test_gcc_method(torch, fcc, config, seconds):
     torch.cuda.synchronize()
     y_ref = O.gcc_corr(O.phat(O.cross_spectrum(X)), rec.N, p.tau_max)
     _check_fp32(t.cpu().numpy(), y.cpu().numpy(), y_ref, p.tau_max)
+
+
+@pytest.mark.parametrize("M,N,tau_max", [(3, 16, 3), (5, 32, 7), (2, 64, 1), (7, 256, 20), (32, 256, 9),
+                                         (16, 2048, 30)])
+def test_gcc_shapes(torch, fcc, M, N, tau_max):
+    """Odd pair counts, the smallest transforms, many mics, and a shape whose
+    spectra do not fit the IFFT kernel's LDS (direct eq. (2) kernel)."""
+    _say(f"GCC shapes M={M} N={N} tau_max={tau_max}")
+    x = random_signals(300 + M, M, 6 * N, kind="gated")
+    p = fcc.Plan(circular_array(M, 0.05), 16000.0, frame_size=N, hop=N // 2, tau_max=tau_max, method="gcc")
+    assert p.I == 2 * tau_max + 1
+    X = O.stft(x, N, N // 2)
+    spec = _oracle_spec_tensor(torch, X, torch.float32)
+    y = p.correlation(spec)
+    t = p.tdoa_from_spectra(spec)
+    torch.cuda.synchronize()
+    y_ref = O.gcc_corr(O.phat(O.cross_spectrum(X)), N, tau_max)
+    _check_fp32(t.cpu().numpy(), y.cpu().numpy(), y_ref, tau_max)
+
+
+@pytest.mark.parametrize("config,seconds", [(1, 1.0), (2, 2.0)])
+def test_gcc_end_to_end(torch, fcc, config, seconds):
+    _say(f"GCC end to end config {config}")
+    rec = make_recording(config, seconds=seconds)
+    p = _plan(fcc, rec, 0, method="gcc")
+    t = p.tdoa(_dev(torch, rec.x))
+    torch.cuda.synchronize()
+    t_ref, y_ref = O.gcc_tdoa(rec.x, rec.N, rec.hop, p.tau_max, return_corr=True)
+    rep = tdoa_report(t.cpu().numpy(), y_ref, p.tau_max, EPS32)
+    assert rep["mismatch_qualified"] == 0, rep
+    assert rep["agreement"] > 0.99, rep
 
 
 # ------------------------------------------------------------- end to end --
