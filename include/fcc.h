@@ -4,12 +4,13 @@
  * Method: F. Grondin et al., "Fast Cross-Correlation for TDoA Estimation on
  * Small Aperture Microphone Arrays", arXiv 2204.13622.  For every STFT frame
  * and every microphone pair the library forms the PHAT-weighted
- * cross-spectrum (Sec. 2, eq. 1 with alpha = 1), projects it on the cropped
- * even/odd bases of the rank-D decomposition of the frequency-to-lag matrix
- * (Sec. 4, eqs. 5-9), expands the coefficients to the lags tau_max .. tau_max
- * through the dictionary, and returns the argmax lag (Sec. 2).  The GCC-PHAT
- * comparator (Sec. 3, eq. 2) shares the front end and evaluates eq. (2) at the
- * same lags directly.
+ * cross-spectrum (Sec. 2, eq. 1, optionally smoothed over frames), projects
+ * it on the cropped even/odd bases of the rank-D decomposition of the
+ * frequency-to-lag matrix (Sec. 4, eqs. 5-9), expands the coefficients to the
+ * lags -tau_max .. tau_max (step 1/r, Sec. 3) through the dictionary, and
+ * returns the argmax lag (Sec. 2), optionally refined by quadratic
+ * interpolation.  The GCC-PHAT comparator (Sec. 3, eq. 2) shares the front end
+ * and evaluates eq. (2) at the same lags through an inverse FFT.
  *
  * Conventions shared by every call
  * --------------------------------
@@ -80,8 +81,8 @@ typedef struct {
   int32_t hop;                    /* frame advance in samples, > 0            */
   int32_t tau_max;                /* 0: ceil(d_max f_S / c) from mic_xyz      */
   int32_t rank;                   /* D in [1, I]; 0 means full rank D = I     */
-  int32_t interp;                 /* r of Sec. 3; only 1 is built             */
-  float alpha;                    /* eq. (1) smoothing; only 1 is built       */
+  int32_t interp;                 /* r of Sec. 3: lag grid step 1/r; 1, 2, 4  */
+  float alpha;                    /* eq. (1) smoothing, (0, 1]; 1 = none      */
   fcc_precision precision;
   fcc_method method;
 } fcc_config;
@@ -104,6 +105,8 @@ typedef struct {
   size_t basis_bytes;             /* size of the device plan buffer           */
   size_t spectrum_bytes_per_frame;/* M * (N/2) * (complex element size)       */
   int32_t spectrum_elem_bytes;    /* 8 (FP32), 4 (BF16/FP16), 2 (FP8)         */
+  int32_t interp;                 /* r                                        */
+  float alpha;
 } fcc_plan_info;
 
 /* Validates the configuration and computes, on the host in FP64, everything a
@@ -111,8 +114,10 @@ typedef struct {
  * the cropped bases p_hat_k (eq. 7) and the dictionary, and the DFT
  * twiddles.  No device call is made.
  * Errors: FCC_ERR_INVALID_ARG (M < 2, non-power-of-two N, hop <= 0,
- * tau_max >= N/4, rank outside [0, I], fs or c <= 0, null pointers),
- * FCC_ERR_UNSUPPORTED (interp != 1, alpha != 1, M > 32),
+ * r tau_max >= N/4, rank outside [0, I], fs or c <= 0, interp not 1, 2 or 4,
+ * alpha outside (0, 1], null pointers),
+ * FCC_ERR_UNSUPPORTED (M > 32, alpha < 1 with a precision other than FP32 or
+ * with method GCC, GCC with r N > 4096),
  * FCC_ERR_BASIS_AMBIGUOUS (rank cuts a cluster of singular values closer than
  * 1e-9 sigma_1, so the rank-D result is not unique). */
 fcc_status fcc_plan_create(const fcc_config* config, fcc_plan* out);
@@ -130,14 +135,16 @@ fcc_status fcc_plan_upload(fcc_plan plan, void* d_basis, hipStream_t stream);
  * or 0 when L < N (frame t covers samples [t hop, t hop + N)). */
 fcc_status fcc_num_frames(fcc_plan plan, int64_t num_samples, int64_t* num_frames);
 
-/* Bytes of workspace fcc_tdoa needs for num_frames frames (the whitened
- * spectra, num_frames * info.spectrum_bytes_per_frame, rounded up to 256). */
+/* Bytes of workspace fcc_tdoa needs for num_frames frames: the spectra,
+ * num_frames * info.spectrum_bytes_per_frame rounded up to 256, and with
+ * alpha < 1 also the smoothing state and fcc_smooth_workspace_bytes. */
 fcc_status fcc_workspace_bytes(fcc_plan plan, int64_t num_frames, size_t* bytes);
 
 /* Sec. 2 front end: Hann-windowed (periodic) real DFT of every frame of every
  * microphone, each bin divided by its magnitude (per-microphone PHAT; at
  * alpha = 1, R_ij / |R_ij| = e_i e_j^* with e = X / |X|).  A bin whose squared
- * magnitude is below FLT_MIN becomes 0.
+ * magnitude is below FLT_MIN becomes 0.  With alpha < 1 the PHAT belongs to
+ * the smoothed cross-spectrum of each pair, and the raw X is written (FP32).
  *   d_x    [M][ld] FP32 audio, row m at d_x + m * ld, L samples used, ld >= L.
  *   d_spec [T][M][N/2] complex slots, interleaved (re, im), in the plan's
  *          precision ("packed real spectrum"): slot 0 holds (e(0), e(N/2)),
@@ -148,16 +155,20 @@ fcc_status fcc_spectra(fcc_plan plan, const void* d_basis, const float* d_x,
                        hipStream_t stream);
 
 /* The whole path from audio: fcc_spectra into d_workspace, then
- * fcc_tdoa_from_spectra.  d_tdoa is [T][P] int32 in samples (lag index minus
- * tau_max).  d_workspace holds fcc_workspace_bytes(T) bytes. */
+ * fcc_tdoa_from_spectra (alpha = 1) or fcc_tdoa_smoothed from R = 0
+ * (alpha < 1).  d_tdoa is [T][P] int32, the lag in units of 1/r sample
+ * (lag index minus r tau_max).  d_workspace holds fcc_workspace_bytes(T)
+ * bytes, 256-byte aligned. */
 fcc_status fcc_tdoa(fcc_plan plan, const void* d_basis, const float* d_x,
                     int64_t num_samples, int64_t ld, int32_t* d_tdoa,
                     void* d_workspace, hipStream_t stream);
 
 /* Pairs, fold (eq. 8), projection (eq. 9), expansion 2 Re{U z} to the I lags
  * and argmax (first index on ties), from whitened spectra laid out as
- * fcc_spectra writes them.  With method GCC, eq. (2) at the I lags replaces
- * the low-rank steps. */
+ * fcc_spectra writes them; d_tdoa [T][P] int32 in units of 1/r sample.  With
+ * method GCC, eq. (2) at the I lags, through an inverse FFT of r N points,
+ * replaces the low-rank steps.  Plans with alpha < 1 use fcc_tdoa_smoothed
+ * (FCC_ERR_UNSUPPORTED here). */
 fcc_status fcc_tdoa_from_spectra(fcc_plan plan, const void* d_basis,
                                  const void* d_spec, int64_t num_frames,
                                  int32_t* d_tdoa, hipStream_t stream);
@@ -179,7 +190,7 @@ fcc_status fcc_coefficients(fcc_plan plan, const void* d_basis, const void* d_sp
                             int64_t num_frames, float* d_coef, hipStream_t stream);
 
 /* The argmax lag refined by the quadratic interpolation of Sec. 2:
- *   d_tau [T][P] FP32 samples, (i* - tau_max) + delta with
+ *   d_tau [T][P] FP32 samples, ((i* - r tau_max) + delta) / r with
  *   delta = (y(i*-1) - y(i*+1)) / (2 (y(i*-1) - 2 y(i*) + y(i*+1))),
  *   and delta = 0 when i* is at either end of the lag window or the
  *   denominator is 0.  FCC method only. */
@@ -193,6 +204,28 @@ fcc_status fcc_tdoa_parabolic(fcc_plan plan, const void* d_basis, const void* d_
  *   dc, ds [I][D] real and imaginary parts of the dictionary U. */
 fcc_status fcc_basis_export(fcc_plan plan, double* sigma, int32_t* is_sym,
                             double* p_hat, double* dc, double* ds);
+
+/* ---- recursive smoothing, alpha < 1 ----------------------------------------
+ * Eq. (1): R(t, f) = (1 - alpha) R(t - 1, f) + alpha X_i(t, f) X_j(t, f)^*
+ * per pair and bin, then R / |R| (0 when |R|^2 < FLT_MIN), fold, projection,
+ * expansion and argmax as above.  The recursion runs over the frames of the
+ * call in order:
+ *   d_spec     [T][M][N/2] raw spectra as fcc_spectra writes them for the plan;
+ *   d_state    [P][N/2 + 1] complex FP32 (interleaved), bins in natural order:
+ *              R before the first frame on entry (zeros for a new stream), R
+ *              after the last frame on return, so consecutive calls continue
+ *              one recursion;
+ *   d_tdoa     [T][P] int32 lag in units of 1/r sample, or NULL;
+ *   d_tau      [T][P] FP32 interpolated lag in samples (as fcc_tdoa_parabolic),
+ *              or NULL;
+ *   d_y        [T][P][I] FP32 correlation, or NULL (at least one output);
+ *   d_workspace fcc_smooth_workspace_bytes(T) bytes, caller-owned.
+ * Limits: rank <= 32, I <= 80 (FCC_ERR_UNSUPPORTED otherwise).  The state
+ * buffer is read and written by the call: calls sharing it must be ordered. */
+fcc_status fcc_smooth_workspace_bytes(fcc_plan plan, int64_t num_frames, size_t* bytes);
+fcc_status fcc_tdoa_smoothed(fcc_plan plan, const void* d_basis, const void* d_spec, int64_t num_frames,
+                             float* d_state, int32_t* d_tdoa, float* d_tau, float* d_y,
+                             void* d_workspace, hipStream_t stream);
 
 /* ---- learned sub-sample TDoA ------------------------------------------------
  * Not from the paper: a multilayer perceptron refining the FCC lag of one

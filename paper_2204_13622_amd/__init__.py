@@ -121,6 +121,58 @@ class Plan:
         _lib.check(self._lib.fcc_workspace_bytes(self._h, int(num_frames), ctypes.byref(out)))
         return out.value
 
+    def smooth_workspace_bytes(self, num_frames: int) -> int:
+        out = ctypes.c_size_t()
+        _lib.check(self._lib.fcc_smooth_workspace_bytes(self._h, int(num_frames), ctypes.byref(out)))
+        return out.value
+
+    @property
+    def r(self) -> int:
+        return self.info.interp
+
+    @property
+    def alpha(self) -> float:
+        return self.info.alpha
+
+    def new_state(self, device=None):
+        """Zero smoothing state R [P, N/2 + 1, 2] float32 (alpha < 1)."""
+        torch = _torch()
+        return torch.zeros((self.P, self.N // 2 + 1, 2), dtype=torch.float32,
+                           device=device if device is not None else "cuda")
+
+    def tdoa_smoothed(self, spec, state=None, tdoa=True, tau=False, y=False, workspace=None):
+        """Recursive smoothing (eq. 1, alpha < 1), per-pair PHAT and FCC over
+        the frames of `spec` (raw spectra from ``spectra``), continuing from
+        `state` [P, N/2 + 1, 2] (zeros when None), which is updated in place.
+        Returns a dict with the requested outputs: 'tdoa' [T, P] int32
+        (1/r sample), 'tau' [T, P] float32 (samples), 'y' [T, P, I] float32,
+        and 'state'."""
+        torch = _torch()
+        T = self._check_spec(spec)
+        dev = spec.device
+        if state is None:
+            state = self.new_state(dev)
+        if (state.dtype != torch.float32 or not state.is_contiguous() or state.device != dev
+                or tuple(state.shape) != (self.P, self.N // 2 + 1, 2)):
+            raise ValueError(f"state must be contiguous float32 [{self.P}, {self.N // 2 + 1}, 2] on the device")
+        out = {"state": state}
+        if tdoa:
+            out["tdoa"] = torch.empty((T, self.P), dtype=torch.int32, device=dev)
+        if tau:
+            out["tau"] = torch.empty((T, self.P), dtype=torch.float32, device=dev)
+        if y:
+            out["y"] = torch.empty((T, self.P, self.I), dtype=torch.float32, device=dev)
+        if workspace is None:
+            workspace = torch.empty(max(self.smooth_workspace_bytes(T), 256), dtype=torch.uint8, device=dev)
+        null = ctypes.c_void_p(0)
+        basis = self.basis_tensor(dev)
+        with torch.cuda.device(dev):
+            _lib.check(self._lib.fcc_tdoa_smoothed(
+                self._h, _ptr(basis), _ptr(spec), T, _ptr(state),
+                _ptr(out["tdoa"]) if tdoa else null, _ptr(out["tau"]) if tau else null,
+                _ptr(out["y"]) if y else null, _ptr(workspace), _stream_handle(dev)))
+        return out
+
     def spectrum_dtype(self):
         torch = _torch()
         return {"fp32": torch.float32, "bf16": torch.bfloat16, "fp16": torch.float16,

@@ -62,7 +62,8 @@ fcc::PairArgs pair_args(const fcc::Plan& p, const void* d_basis, const void* d_s
   a.N = p.N;
   a.I = p.I;
   a.D = p.D;
-  a.tau_max = p.tau_max;
+  a.lag0 = p.r * p.tau_max;
+  a.r = p.r;
   a.precision = p.precision;
   a.method = p.method;
   a.pairs = reinterpret_cast<const uint8_t*>(image_ptr(d_basis, p.layout.pairs));
@@ -75,7 +76,7 @@ fcc::PairArgs pair_args(const fcc::Plan& p, const void* d_basis, const void* d_s
   a.gexp = reinterpret_cast<const float*>(image_ptr(d_basis, p.layout.gexp));
   a.Dfold = p.Dfold;
   a.pfold = reinterpret_cast<const float*>(image_ptr(d_basis, p.layout.pfold));
-  a.twiddle = reinterpret_cast<const float2*>(image_ptr(d_basis, p.layout.twiddle));
+  a.twiddle_r = reinterpret_cast<const float2*>(image_ptr(d_basis, p.layout.twiddle_r));
   a.stream = stream;
   return a;
 }
@@ -92,8 +93,29 @@ fcc_status run_spectra(const fcc::Plan& p, const void* d_basis, const float* d_x
   a.precision = p.precision;
   a.twiddle = reinterpret_cast<const float2*>(image_ptr(d_basis, p.layout.twiddle));
   a.out = d_spec;
+  a.raw = p.alpha < 1.0f;                    // smoothing needs X itself; PHAT comes per pair
   a.stream = stream;
   return hip_status(fcc::launch_stft_phat(a), "stft_phat launch");
+}
+
+size_t up256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// fcc_tdoa's workspace: the spectra, and with smoothing the state and the
+// chunk carries
+struct TdoaWorkspace {
+  size_t spec, state, scratch, total;
+};
+TdoaWorkspace tdoa_workspace(const fcc::Plan& p, int64_t T) {
+  TdoaWorkspace w{};
+  w.spec = 0;
+  w.state = up256(size_t(T) * p.M * (p.N / 2) * p.spec_elem);
+  w.scratch = w.state;
+  w.total = w.state;
+  if (p.alpha < 1.0f && T > 0) {
+    w.scratch = w.state + up256(sizeof(float) * 2 * size_t(p.P) * p.F);
+    w.total = w.scratch + up256(fcc::smooth_scratch_bytes(T, p.P, p.N));
+  }
+  return w;
 }
 
 fcc_status check_audio(const fcc::Plan& p, const float* d_x, int64_t L, int64_t ld) {
@@ -151,6 +173,8 @@ fcc_status fcc_plan_query(fcc_plan plan, fcc_plan_info* info) {
   info->basis_bytes = p.layout.total;
   info->spectrum_bytes_per_frame = size_t(p.M) * (p.N / 2) * p.spec_elem;
   info->spectrum_elem_bytes = p.spec_elem;
+  info->interp = p.r;
+  info->alpha = p.alpha;
   return FCC_OK;
 }
 
@@ -174,8 +198,7 @@ fcc_status fcc_workspace_bytes(fcc_plan plan, int64_t num_frames, size_t* bytes)
   if (!plan || !bytes) return set_error(FCC_ERR_INVALID_ARG, "NULL argument");
   if (num_frames < 0) return set_error(FCC_ERR_INVALID_ARG, "num_frames must be >= 0");
   const fcc::Plan& p = plan->p;
-  const size_t b = size_t(num_frames) * p.M * (p.N / 2) * p.spec_elem;
-  *bytes = (b + 255) & ~size_t(255);
+  *bytes = tdoa_workspace(p, num_frames).total;
   return FCC_OK;
 }
 
@@ -197,6 +220,8 @@ static fcc_status pair_stage(const fcc::Plan& p, const void* d_basis, const void
   if (T < 0) return set_error(FCC_ERR_INVALID_ARG, "num_frames must be >= 0");
   fcc_status st = check_basis(d_basis);
   if (st != FCC_OK) return st;
+  if (p.alpha < 1.0f)
+    return set_error(FCC_ERR_UNSUPPORTED, "with alpha < 1 the pair stage is fcc_tdoa_smoothed");
   if (T == 0) return FCC_OK;
   if ((st = check_spec(p, d_spec)) != FCC_OK) return st;
   if (!d_tdoa && !d_y && !d_coef && !d_tau) return set_error(FCC_ERR_INVALID_ARG, "output pointer is NULL");
@@ -221,6 +246,47 @@ static fcc_status pair_stage(const fcc::Plan& p, const void* d_basis, const void
   if (e == hipErrorInvalidValue)
     return set_error(FCC_ERR_UNSUPPORTED, "shape outside the pair kernel's limits");
   return hip_status(e, "pair kernel launch");
+}
+
+static fcc_status smooth_stage(const fcc::Plan& p, const void* d_basis, const void* d_spec, int64_t T,
+                               float* d_state, int32_t* d_tdoa, float* d_tau, float* d_y, void* d_workspace,
+                               hipStream_t stream) {
+  if (T < 0) return set_error(FCC_ERR_INVALID_ARG, "num_frames must be >= 0");
+  if (p.alpha >= 1.0f) return set_error(FCC_ERR_INVALID_ARG, "the plan has alpha = 1: use fcc_tdoa_from_spectra");
+  fcc_status st = check_basis(d_basis);
+  if (st != FCC_OK) return st;
+  if (T == 0) return FCC_OK;
+  if ((st = check_spec(p, d_spec)) != FCC_OK) return st;
+  if (!d_state || !d_workspace) return set_error(FCC_ERR_INVALID_ARG, "d_state or d_workspace is NULL");
+  if (!d_tdoa && !d_tau && !d_y) return set_error(FCC_ERR_INVALID_ARG, "output pointer is NULL");
+  for (const void* o : {static_cast<const void*>(d_state), static_cast<const void*>(d_tdoa),
+                        static_cast<const void*>(d_tau), static_cast<const void*>(d_y), static_cast<const void*>(d_workspace)})
+    if (o && !aligned(o, 8)) return set_error(FCC_ERR_INVALID_ARG, "pointer misaligned");
+  if (T > int64_t(INT32_MAX)) return set_error(FCC_ERR_UNSUPPORTED, "too many frames for one call");
+  fcc::SmoothArgs a{};
+  a.spec = static_cast<const float2*>(d_spec);
+  a.T = T;
+  a.M = p.M;
+  a.P = p.P;
+  a.N = p.N;
+  a.I = p.I;
+  a.D = p.D;
+  a.Dfold = p.Dfold;
+  a.lag0 = p.r * p.tau_max;
+  a.r = p.r;
+  a.alpha = p.alpha;
+  a.pairs = reinterpret_cast<const uint8_t*>(image_ptr(d_basis, p.layout.pairs));
+  a.pfold = reinterpret_cast<const float*>(image_ptr(d_basis, p.layout.pfold));
+  a.dict = reinterpret_cast<const float*>(image_ptr(d_basis, p.layout.dict));
+  a.state = reinterpret_cast<float2*>(d_state);
+  a.scratch = static_cast<float2*>(d_workspace);
+  a.tdoa = d_tdoa;
+  a.tau = d_tau;
+  a.y = d_y;
+  a.stream = stream;
+  if (!fcc::smooth_supported(a))
+    return set_error(FCC_ERR_UNSUPPORTED, "shape outside the smoothing kernel's limits (rank <= 32, I <= 80)");
+  return hip_status(fcc::launch_smooth(a), "smoothing kernels launch");
 }
 
 fcc_status fcc_tdoa_from_spectra(fcc_plan plan, const void* d_basis, const void* d_spec,
@@ -264,7 +330,30 @@ fcc_status fcc_tdoa(fcc_plan plan, const void* d_basis, const float* d_x, int64_
   if (!d_workspace) return set_error(FCC_ERR_INVALID_ARG, "d_workspace is NULL");
   if ((st = check_spec(p, d_workspace)) != FCC_OK) return st;
   if ((st = run_spectra(p, d_basis, d_x, num_samples, ld, d_workspace, stream)) != FCC_OK) return st;
+  if (p.alpha < 1.0f) {
+    // one recursion over the whole recording, from R = 0
+    const TdoaWorkspace w = tdoa_workspace(p, T);
+    char* ws = static_cast<char*>(d_workspace);
+    float* state = reinterpret_cast<float*>(ws + w.state);
+    if ((st = hip_status(fcc::launch_fill_zero(state, 2 * int64_t(p.P) * p.F, stream), "fill launch")) != FCC_OK)
+      return st;
+    return smooth_stage(p, d_basis, d_workspace, T, state, d_tdoa, nullptr, nullptr, ws + w.scratch, stream);
+  }
   return pair_stage(p, d_basis, d_workspace, T, d_tdoa, nullptr, stream);
+}
+
+fcc_status fcc_smooth_workspace_bytes(fcc_plan plan, int64_t num_frames, size_t* bytes) {
+  if (!plan || !bytes) return set_error(FCC_ERR_INVALID_ARG, "NULL argument");
+  if (num_frames < 0) return set_error(FCC_ERR_INVALID_ARG, "num_frames must be >= 0");
+  *bytes = up256(fcc::smooth_scratch_bytes(num_frames, plan->p.P, plan->p.N));
+  return FCC_OK;
+}
+
+fcc_status fcc_tdoa_smoothed(fcc_plan plan, const void* d_basis, const void* d_spec, int64_t num_frames,
+                             float* d_state, int32_t* d_tdoa, float* d_tau, float* d_y, void* d_workspace,
+                             hipStream_t stream) {
+  if (!plan) return set_error(FCC_ERR_INVALID_ARG, "NULL plan");
+  return smooth_stage(plan->p, d_basis, d_spec, num_frames, d_state, d_tdoa, d_tau, d_y, d_workspace, stream);
 }
 
 fcc_status fcc_basis_export(fcc_plan plan, double* sigma, int32_t* is_sym, double* p_hat, double* dc,

@@ -16,13 +16,34 @@ struct StftArgs {
   fcc_precision precision;
   const float2* twiddle;     // [N] exp(-j 2 pi f / N)
   void* out;                 // [T][M][N/2 + 1] complex, storage format
+  bool raw;                  // true: X itself (FP32 only), false: X / |X|
+  hipStream_t stream;
+};
+
+// pair stage with recursive smoothing, alpha < 1 (eq. 1); FP32 raw spectra
+struct SmoothArgs {
+  const float2* spec;        // [T][M][N/2] raw spectra, packed real layout
+  int64_t T;
+  int M, P, N, I, D, Dfold;
+  int lag0, r;
+  float alpha;
+  const uint8_t* pairs;      // [P][2]
+  const float* pfold;        // [N/4 + 1][Dfold]
+  const float* dict;         // [I][2D]
+  float2* state;             // [P][N/2 + 1] R before the first frame; R after the last on return
+  float2* scratch;           // smooth_scratch_bytes(T, P, N)
+  int32_t* tdoa;             // [T][P] or null
+  float* tau;                // [T][P] interpolated lag (samples) or null
+  float* y;                  // [T][P][I] or null
   hipStream_t stream;
 };
 
 struct PairArgs {
   const void* spec;          // [T][M][F] complex, storage format
   int64_t T;
-  int M, P, N, I, D, tau_max;
+  int M, P, N, I, D;
+  int lag0;                  // index of lag 0 on the grid: r tau_max
+  int r;                     // lag grid spacing 1/r sample (Sec. 3)
   fcc_precision precision;
   fcc_method method;
   const uint8_t* pairs;      // [P][2]
@@ -35,7 +56,7 @@ struct PairArgs {
   const float* gexp;         // [Ipad][Dpad] G = Dc - Ds
   int Dfold;                 // D padded to the FP32 fold kernel's register block
   const float* pfold;        // [N/4 + 1][Dfold] p_hat transposed, zero beyond D
-  const float2* twiddle;     // [N] exp(-j 2 pi n / N)
+  const float2* twiddle_r;   // [r N] exp(-j 2 pi n / (r N))
   int32_t* tdoa;             // [T][P] or null
   float* y;                  // [T][P][I] or null
   float* coef;               // [T][P][2D] projection coefficients (a_k, b_k), or null
@@ -60,6 +81,10 @@ bool pair_mfma_supported(const PairArgs& a);
 bool pair_fold32_supported(const PairArgs& a);
 hipError_t launch_pair_fold32(const PairArgs& a);
 bool gcc_ifft_supported(const PairArgs& a);
+size_t smooth_scratch_bytes(int64_t T, int P, int N);
+bool smooth_supported(const SmoothArgs& a);
+hipError_t launch_smooth(const SmoothArgs& a);
+hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t stream);   // a fill kernel, safe under graph capture
 hipError_t launch_gcc_ifft(const PairArgs& a);
 hipError_t launch_pair_mfma(const PairArgs& a);
 

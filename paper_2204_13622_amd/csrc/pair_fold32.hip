@@ -29,7 +29,7 @@ constexpr int kOutLag = 0, kOutCorr = 1, kOutCoef = 2, kOutParabolic = 3;
 
 template <class S, int DB, int OUT>
 __global__ __launch_bounds__(kThreads) void pair_fold32_kernel(
-    const typename S::T* __restrict__ spec, int M, int P, int N, int I, int tau_max,
+    const typename S::T* __restrict__ spec, int M, int P, int N, int I, int lag0, float inv_r,
     const uint8_t* __restrict__ pairs, const float* __restrict__ pfold /*[N/4+1][DB]*/,
     const float* __restrict__ dict /*[I][2D]*/, int D, int32_t* __restrict__ tdoa,
     float* __restrict__ fout) {
@@ -126,14 +126,14 @@ __global__ __launch_bounds__(kThreads) void pair_fold32_kernel(
           if (ii == bi + 1) y_hi = y;
           prev = y;
         }
-        if (OUT == kOutLag) tdoa[row] = bi - tau_max;
+        if (OUT == kOutLag) tdoa[row] = bi - lag0;                  // units of 1/r sample
         if (OUT == kOutParabolic) {
           // vertex of the parabola through (-1, y_lo), (0, best), (1, y_hi);
           // no refinement at the window edges or on a flat top
           float d = 0.f;
           const float den = y_lo - 2.f * best + y_hi;
           if (bi > 0 && bi < I - 1 && den != 0.f) d = 0.5f * (y_lo - y_hi) / den;
-          fout[row] = (float)(bi - tau_max) + d;
+          fout[row] = ((float)(bi - lag0) + d) * inv_r;              // samples
         }
       }
     }
@@ -158,7 +158,7 @@ hipError_t launch3(const PairArgs& a) {
   }
   float* fout = OUT == kOutCorr ? a.y : (OUT == kOutCoef ? a.coef : a.tau_frac);
   hipLaunchKernelGGL(k, dim3((unsigned)a.T), dim3(kThreads), lds, a.stream,
-                     static_cast<const typename S::T*>(a.spec), a.M, a.P, a.N, a.I, a.tau_max,
+                     static_cast<const typename S::T*>(a.spec), a.M, a.P, a.N, a.I, a.lag0, 1.f / (float)a.r,
                      a.pairs, a.pfold, a.dict, a.D, a.tdoa, fout);
   return hipGetLastError();
 }
@@ -180,6 +180,8 @@ hipError_t launch1(const PairArgs& a) {
     case 16: return launch2<S, 16>(a);
     case 24: return launch2<S, 24>(a);
     case 32: return launch2<S, 32>(a);
+    case 48: return launch2<S, 48>(a);
+    case 64: return launch2<S, 64>(a);
   }
   return hipErrorInvalidValue;
 }
@@ -189,7 +191,7 @@ hipError_t launch1(const PairArgs& a) {
 bool pair_fold32_supported(const PairArgs& a) {
   return a.method == FCC_METHOD_FCC && a.N >= 16 && a.Dfold >= a.D &&
          (a.Dfold == 4 || a.Dfold == 8 || a.Dfold == 12 || a.Dfold == 16 || a.Dfold == 24 ||
-          a.Dfold == 32) &&
+          a.Dfold == 32 || a.Dfold == 48 || a.Dfold == 64) &&
          fold32_lds(a.M, a.N, a.P, a.Dfold) <= 160 * 1024;
 }
 

@@ -77,7 +77,7 @@ constexpr int kPrefetch = 16;   // rounds of 16-byte chunks per lane in flight (
 
 template <class S, int KB, int TT, bool WRITE_Y, int kWaves>
 __global__ __launch_bounds__(64 * kWaves, 2) void pair_mfma_kernel(
-    const typename S::T* __restrict__ spec, int64_t T, int M, int P, int NH, int I, int tau_max,
+    const typename S::T* __restrict__ spec, int64_t T, int M, int P, int NH, int I, int lag0,
     int slab_words, const uint32_t* __restrict__ prow16, const float* __restrict__ gexp,
     const uint8_t* __restrict__ pairs, int32_t* __restrict__ tdoa, float* __restrict__ yout) {
   extern __shared__ uint32_t lds_all[];
@@ -227,7 +227,7 @@ __global__ __launch_bounds__(64 * kWaves, 2) void pair_mfma_kernel(
           bi = tau;
         }
       }
-      if (!WRITE_Y) tdoa[orow] = bi - tau_max;
+      if (!WRITE_Y) tdoa[orow] = bi - lag0;
     }
     wave_sync();   // the slab is rewritten by the next frame
   }
@@ -272,7 +272,7 @@ hipError_t launch5(const PairArgs& a) {
   const int64_t blocks = need < cap ? need : cap;
   hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * WV), lds, a.stream,
                      static_cast<const typename S::T*>(a.spec), a.T, a.M, a.P, a.N / 2, a.I,
-                     a.tau_max, slab_words(a), reinterpret_cast<const uint32_t*>(a.prow16), a.gexp,
+                     a.lag0, slab_words(a), reinterpret_cast<const uint32_t*>(a.prow16), a.gexp,
                      a.pairs, a.tdoa, a.y);
   return hipGetLastError();
 }
@@ -286,7 +286,8 @@ template <class S, int KB>
 hipError_t launch3(const PairArgs& a) {
   const bool wy = a.y != nullptr;
   if (a.I <= 16) return wy ? launch4<S, KB, 1, true>(a) : launch4<S, KB, 1, false>(a);
-  return wy ? launch4<S, KB, 2, true>(a) : launch4<S, KB, 2, false>(a);
+  if (a.I <= 32) return wy ? launch4<S, KB, 2, true>(a) : launch4<S, KB, 2, false>(a);
+  return wy ? launch4<S, KB, 3, true>(a) : launch4<S, KB, 3, false>(a);
 }
 
 template <class S>
@@ -310,7 +311,7 @@ bool pair_mfma_supported(const PairArgs& a) {
   const bool kb_ok = a.Dpad % 4 == 0 && (kb == 1 || kb == 2 || kb == 3 || kb == 4 || kb == 6 || kb == 8);
   return a.method == FCC_METHOD_FCC && a.precision != FCC_FP32 && a.M <= 16 && a.N >= 32 &&
          (reinterpret_cast<uintptr_t>(a.spec) % 16) == 0 &&
-         a.D <= a.Dpad && kb_ok && a.I <= 32 && block_waves(a) > 0;
+         a.D <= a.Dpad && kb_ok && a.I <= 48 && block_waves(a) > 0;
 }
 
 hipError_t launch_pair_mfma(const PairArgs& a) {

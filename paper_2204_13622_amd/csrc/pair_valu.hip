@@ -18,7 +18,7 @@ constexpr int kThreads = 256;
 
 template <class S, int IMAX, bool WRITE_Y, bool GCC>
 __global__ __launch_bounds__(kThreads) void pair_valu_kernel(
-    const typename S::T* __restrict__ spec, int M, int P, int N, int I, int D, int tau_max,
+    const typename S::T* __restrict__ spec, int M, int P, int N, int I, int D, int lag0,
     const uint8_t* __restrict__ pairs, const float* __restrict__ basis,
     const float* __restrict__ dict, const float2* __restrict__ lagw,
     int32_t* __restrict__ tdoa, float* __restrict__ yout) {
@@ -116,7 +116,7 @@ __global__ __launch_bounds__(kThreads) void pair_valu_kernel(
       for (int ii = 1; ii < IMAX; ++ii) {
         if (ii < I && y[ii] > best) { best = y[ii]; bi = ii; }
       }
-      tdoa[row] = bi - tau_max;
+      tdoa[row] = bi - lag0;
     }
   }
 }
@@ -131,7 +131,7 @@ hipError_t launch4(const PairArgs& a, size_t lds) {
   }
   hipLaunchKernelGGL(k, dim3((unsigned)a.T), dim3(kThreads), lds, a.stream,
                      static_cast<const typename S::T*>(a.spec), a.M, a.P, a.N, a.I, a.D,
-                     a.tau_max, a.pairs, a.basis32, a.dict, a.lagw, a.tdoa, a.y);
+                     a.lag0, a.pairs, a.basis32, a.dict, a.lagw, a.tdoa, a.y);
   return hipGetLastError();
 }
 

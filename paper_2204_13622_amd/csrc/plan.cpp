@@ -223,8 +223,15 @@ fcc_status build_plan(const fcc_config& cfg, Plan& pl, std::string& err) {
   if (cfg.hop <= 0) return fail(err, FCC_ERR_INVALID_ARG, "hop must be > 0");
   if (!(cfg.fs > 0) || !std::isfinite(cfg.fs)) return fail(err, FCC_ERR_INVALID_ARG, "fs must be > 0");
   if (!(cfg.c > 0) || !std::isfinite(cfg.c)) return fail(err, FCC_ERR_INVALID_ARG, "c must be > 0");
-  if (cfg.interp != 1) return fail(err, FCC_ERR_UNSUPPORTED, "only interp = 1 is built");
-  if (cfg.alpha != 1.0f) return fail(err, FCC_ERR_UNSUPPORTED, "only alpha = 1 is built");
+  if (cfg.interp != 1 && cfg.interp != 2 && cfg.interp != 4)
+    return fail(err, FCC_ERR_INVALID_ARG, "interp must be 1, 2 or 4");
+  if (cfg.method == FCC_METHOD_GCC && cfg.interp * cfg.frame_size > 4096)
+    return fail(err, FCC_ERR_UNSUPPORTED, "GCC inverse transforms above 4096 points are not built");
+  if (!(cfg.alpha > 0.0f && cfg.alpha <= 1.0f)) return fail(err, FCC_ERR_INVALID_ARG, "alpha must be in (0, 1]");
+  if (cfg.alpha < 1.0f && cfg.precision != FCC_FP32)
+    return fail(err, FCC_ERR_UNSUPPORTED, "alpha < 1 is built for FP32 spectra only");
+  if (cfg.alpha < 1.0f && cfg.method != FCC_METHOD_FCC)
+    return fail(err, FCC_ERR_UNSUPPORTED, "alpha < 1 is built for the FCC method only");
   if (cfg.precision < FCC_FP32 || cfg.precision > FCC_FP8_E4M3)
     return fail(err, FCC_ERR_INVALID_ARG, "unknown precision");
   if (cfg.method != FCC_METHOD_FCC && cfg.method != FCC_METHOD_GCC)
@@ -262,16 +269,16 @@ fcc_status build_plan(const fcc_config& cfg, Plan& pl, std::string& err) {
       }
     pl.tau_max = int(std::ceil(dmax * pl.fs / pl.c));
   }
-  if (pl.tau_max >= pl.m)
-    return fail(err, FCC_ERR_INVALID_ARG, "tau_max must be < N/4 (lag window inside the frame)");
+  if (pl.r * pl.tau_max >= pl.m)
+    return fail(err, FCC_ERR_INVALID_ARG, "r tau_max must be < N/4 (lag window inside the frame)");
   pl.I = 2 * pl.r * pl.tau_max + 1;
   if (pl.method == FCC_METHOD_GCC) {
     pl.D = pl.I;
   } else {
     pl.D = cfg.rank == 0 ? pl.I : cfg.rank;
-    if (pl.D > pl.I) return fail(err, FCC_ERR_INVALID_ARG, "rank must be <= I = 2 tau_max + 1");
+    if (pl.D > pl.I) return fail(err, FCC_ERR_INVALID_ARG, "rank must be <= I = 2 r tau_max + 1");
+    if (pl.D > 64) return fail(err, FCC_ERR_UNSUPPORTED, "rank above 64 is not built");
   }
-  if (pl.D > 64) return fail(err, FCC_ERR_UNSUPPORTED, "rank above 64 is not built");
   pl.Ds = (pl.D + 1) / 2;
   pl.Da = pl.D / 2;
 
@@ -333,6 +340,7 @@ fcc_status build_plan(const fcc_config& cfg, Plan& pl, std::string& err) {
   ImageLayout& L = pl.layout;
   size_t off = 0;
   L.twiddle = off; off = align256(off + 2 * sizeof(float) * pl.N);
+  L.twiddle_r = off; off = align256(off + 2 * sizeof(float) * size_t(pl.r) * pl.N);
   L.pairs = off;   off = align256(off + 2 * size_t(pl.P));
   L.basis32 = off; off = align256(off + sizeof(float) * size_t(D) * (m + 1));
   L.dict = off;    off = align256(off + sizeof(float) * size_t(I) * 2 * D);
@@ -351,7 +359,7 @@ fcc_status build_plan(const fcc_config& cfg, Plan& pl, std::string& err) {
   L.prow16 = off;  off = align256(off + 2 * sizeof(uint16_t) * size_t(pl.Dpad) * NH);
   L.gexp = off;    off = align256(off + sizeof(float) * size_t(pl.Ipad) * pl.Dpad);
   pl.Dfold = 0;
-  for (int c : {4, 8, 12, 16, 24, 32})
+  for (int c : {4, 8, 12, 16, 24, 32, 48, 64})
     if (D <= c) { pl.Dfold = c; break; }
   L.pfold = off;   off = align256(off + sizeof(float) * size_t(pl.Dfold) * (m + 1));
   L.total = off;
@@ -367,6 +375,12 @@ fcc_status build_plan(const fcc_config& cfg, Plan& pl, std::string& err) {
     unit_circle(f, pl.N, cs, sn);
     fput(L.twiddle, 2 * f, cs);
     fput(L.twiddle, 2 * f + 1, -sn);
+  }
+  for (int f = 0; f < pl.r * pl.N; ++f) {
+    double cs, sn;
+    unit_circle(f, pl.r * pl.N, cs, sn);
+    fput(L.twiddle_r, 2 * f, cs);
+    fput(L.twiddle_r, 2 * f + 1, -sn);
   }
   {
     int p = 0;

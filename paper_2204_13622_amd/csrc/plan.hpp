@@ -14,6 +14,7 @@ namespace fcc {
 // Offsets (bytes) of the tables inside the device image; each is 256-aligned.
 struct ImageLayout {
   size_t twiddle = 0;     // float2 [N]          exp(-j 2 pi f / N), full circle
+  size_t twiddle_r = 0;   // float2 [r N]        exp(-j 2 pi f / (r N)) (GCC inverse transform)
   size_t pairs = 0;       // uint8 [P][2]        (i, j), lexicographic
   size_t basis32 = 0;     // float [D][Bs]       p_hat rows, Bs = N/4 + 1
   size_t dict = 0;        // float [I][2D]       (2 Dc, -2 Ds) interleaved per k
@@ -48,7 +49,7 @@ struct Plan {
   ImageLayout layout;
   std::vector<unsigned char> image;
   int Dpad = 0, Ipad = 0;           // D and I rounded up to the MFMA tiles (4, 16)
-  int Dfold = 0;                    // D rounded up to 4, 8, 12, 16, 24 or 32 (0 above 32)
+  int Dfold = 0;                    // D rounded up to 4, 8, 12, 16, 24, 32, 48 or 64
   int spec_elem = 8;                // bytes per complex spectrum element
 };
 

@@ -16,6 +16,9 @@
 // normalisation.  Twiddles (and the window, through its cosine) come from a
 // full-circle FP64-computed table staged in LDS.
 //
+// With recursive smoothing (alpha < 1) the PHAT belongs to each pair's
+// smoothed cross-spectrum, so the raw spectra X are written instead (FP32).
+//
 // Output layout ("packed real spectrum"): N/2 complex slots per microphone;
 // slot 0 holds (e(0), e(N/2)), both real, slot f holds e(f) for 0 < f < N/2.
 #include "device_common.hpp"
@@ -43,7 +46,7 @@ __device__ __forceinline__ float phat_real(float x) {
   return x > 0.f ? 1.f : -1.f;
 }
 
-template <int N, class S>
+template <int N, class S, bool RAW>
 __global__ __launch_bounds__(kThreads) void stft_phat_kernel(
     const float* __restrict__ x, int64_t ld, int M, int hop, int64_t nfft,
     const float2* __restrict__ twiddle, typename S::T* __restrict__ out) {
@@ -116,7 +119,8 @@ __global__ __launch_bounds__(kThreads) void stft_phat_kernel(
     if (f == 0) {
       // X(0) = Re Z(0) + Im Z(0), X(N/2) = Re Z(0) - Im Z(0); both real
       const float2 z0 = buf[0];
-      dst[0] = spec_encode<S>(make_float2(phat_real(z0.x + z0.y), phat_real(z0.x - z0.y)));
+      if (RAW) dst[0] = spec_encode<S>(make_float2(z0.x + z0.y, z0.x - z0.y));
+      else dst[0] = spec_encode<S>(make_float2(phat_real(z0.x + z0.y), phat_real(z0.x - z0.y)));
       continue;
     }
     const float2 zf = buf[pidx(f)];
@@ -126,32 +130,32 @@ __global__ __launch_bounds__(kThreads) void stft_phat_kernel(
     const float2 wo = cmul(tw[f], o);
     const float2 Xa = cadd(e, wo);
     const float2 Xb = make_float2(e.x - wo.x, wo.y - e.y);
-    dst[f] = spec_encode<S>(phat_complex(Xa));
-    if (f != NH - f) dst[NH - f] = spec_encode<S>(phat_complex(Xb));
+    dst[f] = spec_encode<S>(RAW ? Xa : phat_complex(Xa));
+    if (f != NH - f) dst[NH - f] = spec_encode<S>(RAW ? Xb : phat_complex(Xb));
   }
 }
 
-template <int N, class S>
+template <int N, class S, bool RAW>
 hipError_t launch_n(const StftArgs& a) {
   constexpr int FPB = kThreads / Radices<N / 2>::LF;
   const int64_t nfft = a.T * a.M;
   const int64_t blocks = (nfft + FPB - 1) / FPB;
-  hipLaunchKernelGGL((stft_phat_kernel<N, S>), dim3((unsigned)blocks), dim3(kThreads), 0, a.stream,
+  hipLaunchKernelGGL((stft_phat_kernel<N, S, RAW>), dim3((unsigned)blocks), dim3(kThreads), 0, a.stream,
                      a.x, a.ld, a.M, a.hop, nfft, a.twiddle, static_cast<typename S::T*>(a.out));
   return hipGetLastError();
 }
 
-template <class S>
+template <class S, bool RAW = false>
 hipError_t launch_s(const StftArgs& a) {
   switch (a.N) {
-    case 16: return launch_n<16, S>(a);
-    case 32: return launch_n<32, S>(a);
-    case 64: return launch_n<64, S>(a);
-    case 128: return launch_n<128, S>(a);
-    case 256: return launch_n<256, S>(a);
-    case 512: return launch_n<512, S>(a);
-    case 1024: return launch_n<1024, S>(a);
-    case 2048: return launch_n<2048, S>(a);
+    case 16: return launch_n<16, S, RAW>(a);
+    case 32: return launch_n<32, S, RAW>(a);
+    case 64: return launch_n<64, S, RAW>(a);
+    case 128: return launch_n<128, S, RAW>(a);
+    case 256: return launch_n<256, S, RAW>(a);
+    case 512: return launch_n<512, S, RAW>(a);
+    case 1024: return launch_n<1024, S, RAW>(a);
+    case 2048: return launch_n<2048, S, RAW>(a);
     default: return hipErrorInvalidValue;
   }
 }
@@ -160,6 +164,7 @@ hipError_t launch_s(const StftArgs& a) {
 
 hipError_t launch_stft_phat(const StftArgs& a) {
   if (a.T == 0) return hipSuccess;
+  if (a.raw) return a.precision == FCC_FP32 ? launch_s<SpecF32, true>(a) : hipErrorInvalidValue;
   switch (a.precision) {
     case FCC_FP32: return launch_s<SpecF32>(a);
     case FCC_BF16: return launch_s<SpecBF16>(a);

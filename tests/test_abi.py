@@ -51,8 +51,13 @@ def test_status_strings(fcc):
     (dict(c=0.0), "FCC_ERR_INVALID_ARG"),
     (dict(rank=10), "FCC_ERR_INVALID_ARG"),          # I = 9 for the 5 cm square
     (dict(tau_max=128), "FCC_ERR_INVALID_ARG"),      # must stay below N/4
-    (dict(interp=2), "FCC_ERR_UNSUPPORTED"),
-    (dict(alpha=0.1), "FCC_ERR_UNSUPPORTED"),
+    (dict(interp=3), "FCC_ERR_INVALID_ARG"),
+    (dict(interp=4, tau_max=32), "FCC_ERR_INVALID_ARG"),   # r tau_max must stay below N/4
+    (dict(alpha=0.0), "FCC_ERR_INVALID_ARG"),
+    (dict(alpha=1.5), "FCC_ERR_INVALID_ARG"),
+    (dict(alpha=0.1, precision="bf16"), "FCC_ERR_UNSUPPORTED"),
+    (dict(alpha=0.1, method="gcc"), "FCC_ERR_UNSUPPORTED"),
+    (dict(interp=4, frame_size=2048, hop=512, method="gcc"), "FCC_ERR_UNSUPPORTED"),
     (dict(mic_xyz=circular_array(33, 0.05)), "FCC_ERR_UNSUPPORTED"),
 ])
 def test_invalid_configs(fcc, kw, status):
@@ -84,6 +89,20 @@ def test_plan_query(fcc):
     assert g.rank == g.I == 9
 
 
+def test_interp_and_alpha_plans(fcc):
+    # the paper's operating point: tau_max = 8, r = 2 -> I = 33 (Sec. 3 and 5)
+    p = fcc.Plan(np.array([[0, 0, 0], [0.15, 0, 0]]), 16000.0, c=335.0, frame_size=512, hop=256,
+                 tau_max=8, rank=8, interp=2, alpha=0.1)
+    assert (p.tau_max, p.I, p.rank, p.info.interp) == (8, 33, 8, 2)
+    assert abs(p.info.alpha - 0.1) < 1e-7
+    assert p.info.spectrum_elem_bytes == 8
+    # alpha < 1: the whole-path workspace also holds the state and the chunk carries
+    assert p.workspace_bytes(100) > 100 * p.info.spectrum_bytes_per_frame
+    assert p.smooth_workspace_bytes(100) > 0 and p.smooth_workspace_bytes(0) == 0
+    g = fcc.Plan(circular_array(4, 0.05), 16000.0, frame_size=1024, hop=256, interp=4, method="gcc")
+    assert g.I == 8 * g.tau_max + 1
+
+
 def _operator(e, N):
     """Rank-D frequency-to-lag operator U S V^T rebuilt from exported tables."""
     m, F = N // 4, N // 2 + 1
@@ -96,6 +115,21 @@ def _operator(e, N):
         V[k, N // 2 - f] = v[:m] if e["is_sym"][k] else -v[:m]
         V[k, m] = v[m]
     return (e["Dc"] + 1j * e["Ds"]) @ (e["sigma"][:, None] * V)
+
+
+@pytest.mark.parametrize("r,tau_max,D", [(2, 8, 8), (2, 8, 16), (2, 4, 17), (4, 3, 9), (2, 8, 33)])
+def test_host_basis_matches_oracle_interp(fcc, r, tau_max, D):
+    p = fcc.Plan(np.array([[0, 0, 0], [0.15, 0, 0]]), 16000.0, frame_size=512, hop=256,
+                 tau_max=tau_max, rank=D, interp=r)
+    assert p.I == 2 * r * tau_max + 1
+    e = p.basis_export()
+    B = O.fcc_basis(512, tau_max, D, r)
+    assert list(e["is_sym"]) == list(B.is_sym)
+    assert np.abs(e["sigma"] - B.sigma).max() < 1e-12 * B.sigma[0]
+    Ob = (B.Dc + 1j * B.Ds) @ (B.sigma[:, None] * B.v_full)
+    assert np.abs(_operator(e, 512) - Ob).max() < 1e-12 * B.sigma[0]
+    assert np.array_equal(e["Dc"], e["Dc"][::-1])
+    assert np.array_equal(e["Ds"], -e["Ds"][::-1])
 
 
 @pytest.mark.parametrize("xyz,fs,N,D", [
