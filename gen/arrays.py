@@ -258,3 +258,34 @@ def fractional_delay_frames(seed: int, count: int, M: int = 8, radius: float = 0
         x[:, e0 * N:(e0 + E) * N] = sig.transpose(1, 0, 2).reshape(M, E * N)
         delays[e0:e0 + E] = d
     return x, delays, xyz
+
+
+def pair_room(seed: int, d: float, seconds: float = 1.0, fs: float = 16000.0,
+              c_range=(335.0, 350.0), rt60_range=(0.1, 0.6), drr_db=(0.0, 10.0),
+              snr_db=(10.0, 30.0)):
+    """Two microphones `d` metres apart on the x axis and a white far-field
+    source at angle theta from that axis (uniform in (0, pi)), with a speed of
+    sound uniform in `c_range`; each mic hears the fractionally delayed direct
+    path plus its own exponentially decaying reverberant tail (RT60 and
+    direct-to-reverberant ratio uniform in their ranges) and white sensor noise.
+
+    Returns (x [2][L] float32, tdoa, theta, c) with tdoa = t_0 - t_1 =
+    d cos(theta) fs / c in samples."""
+    from scipy.signal import fftconvolve
+    rng = np.random.default_rng(seed)
+    L = int(round(seconds * fs))
+    theta = rng.uniform(0.0, np.pi)
+    c = rng.uniform(*c_range)
+    tdoa = d * np.cos(theta) * fs / c
+    pad = 64
+    s = rng.standard_normal(L + 2 * pad)
+    delays = (0.5 * tdoa, -0.5 * tdoa)                   # arrival times about the centre
+    rt60 = rng.uniform(*rt60_range)
+    x = np.empty((2, L))
+    for m in range(2):
+        direct = fractional_delay(s, delays[m], pad, L)
+        h = _reverb_fir(rng, fs, rt60)                    # unit direct path, unit-energy tail
+        h[1:] *= np.sqrt(10.0 ** (-rng.uniform(*drr_db) / 10.0))
+        rev = fftconvolve(direct, h)[:L]
+        x[m] = rev + _snr_noise(rng, rev, rng.uniform(*snr_db))
+    return x.astype(np.float32), float(tdoa), float(theta), float(c)
