@@ -289,3 +289,13 @@ def pair_room(seed: int, d: float, seconds: float = 1.0, fs: float = 16000.0,
         rev = fftconvolve(direct, h)[:L]
         x[m] = rev + _snr_noise(rng, rev, rng.uniform(*snr_db))
     return x.astype(np.float32), float(tdoa), float(theta), float(c)
+
+
+def sphere_grid(G: int, upper: bool = False) -> np.ndarray:
+    """G unit vectors spread evenly over the sphere (or the upper half, z >= 0)
+    by the Fibonacci lattice; [G][3] float64."""
+    k = np.arange(G, dtype=np.float64) + 0.5
+    z = 1.0 - k / G if upper else 1.0 - 2.0 * k / G
+    rho = np.sqrt(np.maximum(0.0, 1.0 - z * z))
+    phi = np.pi * (3.0 - np.sqrt(5.0)) * k
+    return np.stack([rho * np.cos(phi), rho * np.sin(phi), z], axis=1)
