@@ -227,6 +227,24 @@ fcc_status fcc_tdoa_smoothed(fcc_plan plan, const void* d_basis, const void* d_s
                              float* d_state, int32_t* d_tdoa, float* d_tau, float* d_y,
                              void* d_workspace, hipStream_t stream);
 
+/* ---- direction of arrival ---------------------------------------------------
+ * Sec. 6 names the next step: the TDoAs of every pair of an array feeding a
+ * search over direction candidates.  For unit directions u_g the far-field
+ * TDoA of pair (i, j) is tau = (r_j - r_i) . u_g f_S / c samples (the sign
+ * convention of d_tdoa), at fractional lag index
+ *   q[p][g] = clamp(r tau + r tau_max, 0, I - 1)
+ * on the correlation's grid.  fcc_doa_table computes q on the host in FP64
+ * (dirs [G][3] unit vectors and table [P][G] FP32, both host memory owned by
+ * the caller).  fcc_doa scores every direction by the sum
+ * over pairs of y at q[p][g], interpolated linearly between neighbouring
+ * lags, from d_y [T][P][I] (fcc_correlation or fcc_tdoa_smoothed) and the
+ * table copied to the device (d_table [P][G]); d_doa [T] int32 receives the
+ * first direction of largest score and d_score [T][G] FP32 (may be NULL) the
+ * scores.  FCC_ERR_UNSUPPORTED when one frame's correlations exceed 48 KB. */
+fcc_status fcc_doa_table(fcc_plan plan, const double* dirs, int32_t num_dirs, float* table);
+fcc_status fcc_doa(fcc_plan plan, const float* d_y, int64_t num_frames, const float* d_table, int32_t num_dirs,
+                   int32_t* d_doa, float* d_score, hipStream_t stream);
+
 /* ---- learned sub-sample TDoA ------------------------------------------------
  * Not from the paper: a multilayer perceptron refining the FCC lag of one
  * pair-frame from its projection coefficients (fcc_coefficients).  One row =

@@ -173,6 +173,35 @@ class Plan:
                 _ptr(out["y"]) if y else null, _ptr(workspace), _stream_handle(dev)))
         return out
 
+    def doa_table(self, dirs, device=None):
+        """Fractional lag index of every pair for every unit direction,
+        [P, G] float32 on `device` (built on the host in FP64)."""
+        torch = _torch()
+        d = np.ascontiguousarray(np.asarray(dirs, dtype=np.float64).reshape(-1, 3))
+        table = np.empty((self.P, d.shape[0]), dtype=np.float32)
+        _lib.check(self._lib.fcc_doa_table(self._h, d.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                           d.shape[0], table.ctypes.data_as(ctypes.c_void_p)))
+        return torch.from_numpy(table).to(device if device is not None else "cuda")
+
+    def doa(self, y, table, score=False):
+        """First best direction [T] int32 for correlations y [T, P, I]; with
+        score=True also the scores [T, G].  Returns (doa, scores or None)."""
+        torch = _torch()
+        if y.dtype != torch.float32 or not y.is_contiguous() or y.dim() != 3 or \
+                tuple(y.shape[1:]) != (self.P, self.I):
+            raise ValueError(f"y must be contiguous float32 [T, {self.P}, {self.I}]")
+        if table.dtype != torch.float32 or not table.is_contiguous() or table.dim() != 2 or \
+                table.shape[0] != self.P or table.device != y.device:
+            raise ValueError("table must be the plan's [P, G] float32 table on y's device")
+        T, G = y.shape[0], table.shape[1]
+        out = torch.empty(T, dtype=torch.int32, device=y.device)
+        sc = torch.empty((T, G), dtype=torch.float32, device=y.device) if score else None
+        with torch.cuda.device(y.device):
+            _lib.check(self._lib.fcc_doa(self._h, _ptr(y), T, _ptr(table), G, _ptr(out),
+                                         _ptr(sc) if score else ctypes.c_void_p(0),
+                                         _stream_handle(y.device)))
+        return out, sc
+
     def spectrum_dtype(self):
         torch = _torch()
         return {"fp32": torch.float32, "bf16": torch.bfloat16, "fp16": torch.float16,

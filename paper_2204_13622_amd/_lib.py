@@ -19,7 +19,7 @@ EXPORTS = ("fcc_plan_create", "fcc_plan_destroy", "fcc_plan_query", "fcc_plan_up
            "fcc_tdoa_from_spectra", "fcc_correlation", "fcc_coefficients", "fcc_tdoa_parabolic",
            "fcc_basis_export", "fcc_mlp_num_params", "fcc_mlp_workspace_bytes", "fcc_mlp_forward",
            "fcc_mlp_backward", "fcc_mlp_adam", "fcc_learned_workspace_bytes", "fcc_tdoa_learned",
-           "fcc_smooth_workspace_bytes", "fcc_tdoa_smoothed",
+           "fcc_smooth_workspace_bytes", "fcc_tdoa_smoothed", "fcc_doa_table", "fcc_doa",
            "fcc_status_string", "fcc_last_error")
 
 
@@ -86,6 +86,8 @@ def load() -> ctypes.CDLL:
         "fcc_mlp_workspace_bytes": [ctypes.c_int32, ctypes.c_int32, i64, ctypes.POINTER(ctypes.c_size_t)],
         "fcc_mlp_forward": [vp, ctypes.c_int32, ctypes.c_int32, vp, i64, vp, vp, vp],
         "fcc_mlp_backward": [vp, ctypes.c_int32, ctypes.c_int32, vp, vp, i64, vp, vp, vp, vp, vp],
+        "fcc_doa_table": [vp, dp, ctypes.c_int32, vp],
+        "fcc_doa": [vp, vp, i64, vp, ctypes.c_int32, vp, vp, vp],
         "fcc_smooth_workspace_bytes": [vp, i64, ctypes.POINTER(ctypes.c_size_t)],
         "fcc_tdoa_smoothed": [vp, vp, vp, i64, vp, vp, vp, vp, vp, vp],
         "fcc_learned_workspace_bytes": [vp, ctypes.c_int32, i64, ctypes.POINTER(ctypes.c_size_t)],

@@ -477,6 +477,51 @@ fcc_status fcc_tdoa_learned(fcc_plan plan, const void* d_basis, const void* d_sp
                     "select launch");
 }
 
+fcc_status fcc_doa_table(fcc_plan plan, const double* dirs, int32_t num_dirs, float* table) {
+  if (!plan || !dirs || !table) return set_error(FCC_ERR_INVALID_ARG, "NULL argument");
+  if (num_dirs < 1) return set_error(FCC_ERR_INVALID_ARG, "num_dirs must be >= 1");
+  const fcc::Plan& p = plan->p;
+  for (int64_t e = 0; e < 3 * int64_t(num_dirs); ++e)
+    if (!std::isfinite(dirs[e])) return set_error(FCC_ERR_INVALID_ARG, "a direction has a non-finite entry");
+  const double scale = p.r * p.fs / p.c, lag0 = double(p.r) * p.tau_max, top = double(p.I - 1);
+  int pp = 0;
+  for (int i = 0; i < p.M; ++i)
+    for (int j = i + 1; j < p.M; ++j, ++pp) {
+      const double bx = p.xyz[3 * j] - p.xyz[3 * i], by = p.xyz[3 * j + 1] - p.xyz[3 * i + 1],
+                   bz = p.xyz[3 * j + 2] - p.xyz[3 * i + 2];
+      for (int g = 0; g < num_dirs; ++g) {
+        const double* u = dirs + 3 * size_t(g);
+        double qv = scale * (bx * u[0] + by * u[1] + bz * u[2]) + lag0;
+        qv = qv < 0.0 ? 0.0 : (qv > top ? top : qv);
+        table[size_t(pp) * num_dirs + g] = float(qv);
+      }
+    }
+  return FCC_OK;
+}
+
+fcc_status fcc_doa(fcc_plan plan, const float* d_y, int64_t num_frames, const float* d_table, int32_t num_dirs,
+                   int32_t* d_doa, float* d_score, hipStream_t stream) {
+  if (!plan) return set_error(FCC_ERR_INVALID_ARG, "NULL plan");
+  if (num_frames < 0 || num_dirs < 1) return set_error(FCC_ERR_INVALID_ARG, "num_frames >= 0 and num_dirs >= 1");
+  if (num_frames == 0) return FCC_OK;
+  if (!d_y || !d_table || !d_doa) return set_error(FCC_ERR_INVALID_ARG, "NULL pointer");
+  for (const void* o : {static_cast<const void*>(d_y), static_cast<const void*>(d_table),
+                        static_cast<const void*>(d_doa), static_cast<const void*>(d_score)})
+    if (o && !aligned(o, 4)) return set_error(FCC_ERR_INVALID_ARG, "pointer misaligned");
+  fcc::DoaArgs a{};
+  a.y = d_y;
+  a.T = num_frames;
+  a.P = plan->p.P;
+  a.I = plan->p.I;
+  a.table = d_table;
+  a.G = num_dirs;
+  a.doa = d_doa;
+  a.score = d_score;
+  a.stream = stream;
+  if (!fcc::doa_supported(a)) return set_error(FCC_ERR_UNSUPPORTED, "one frame's correlations exceed 48 KB");
+  return hip_status(fcc::launch_doa(a), "doa launch");
+}
+
 const char* fcc_status_string(fcc_status status) {
   switch (status) {
     case FCC_OK: return "FCC_OK";

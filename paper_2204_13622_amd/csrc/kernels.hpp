@@ -20,6 +20,18 @@ struct StftArgs {
   hipStream_t stream;
 };
 
+// direction-of-arrival search over a direction grid
+struct DoaArgs {
+  const float* y;            // [T][P][I] correlations
+  int64_t T;
+  int P, I;
+  const float* table;        // [P][G] fractional lag index per pair and direction
+  int G;
+  int32_t* doa;              // [T] first best direction
+  float* score;              // [T][G] or null
+  hipStream_t stream;
+};
+
 // pair stage with recursive smoothing, alpha < 1 (eq. 1); FP32 raw spectra
 struct SmoothArgs {
   const float2* spec;        // [T][M][N/2] raw spectra, packed real layout
@@ -84,6 +96,8 @@ bool gcc_ifft_supported(const PairArgs& a);
 size_t smooth_scratch_bytes(int64_t T, int P, int N);
 bool smooth_supported(const SmoothArgs& a);
 hipError_t launch_smooth(const SmoothArgs& a);
+bool doa_supported(const DoaArgs& a);
+hipError_t launch_doa(const DoaArgs& a);
 hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t stream);   // a fill kernel, safe under graph capture
 hipError_t launch_gcc_ifft(const PairArgs& a);
 hipError_t launch_pair_mfma(const PairArgs& a);

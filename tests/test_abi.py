@@ -181,3 +181,23 @@ def test_mlp_host_queries(fcc):
     assert learned_workspace_bytes(p, 128, 100) % 256 == 0
     with pytest.raises(fcc.FccError):
         learned_workspace_bytes(p, 100, 10)
+
+
+def test_doa_table_matches_oracle(fcc):
+    import oracle.doa_oracle as DO
+    from gen import sphere_grid
+    xyz = np.vstack([circular_array(6, 0.05), [[0.0, 0.0, 0.05]]])
+    dirs = sphere_grid(300)
+    for r in (1, 2):
+        p = fcc.Plan(xyz, 16000.0, frame_size=512, hop=128, rank=5, interp=r)
+        lib = fcc._lib.load()
+        d = np.ascontiguousarray(dirs)
+        tab = np.empty((p.P, d.shape[0]), dtype=np.float32)
+        assert lib.fcc_doa_table(p._h, d.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), d.shape[0],
+                                 tab.ctypes.data_as(ctypes.c_void_p)) == 0
+        q = DO.lag_positions(xyz, dirs, 16000.0, 343.0, p.tau_max, r)
+        assert np.abs(tab - q).max() <= 4e-7 * p.I          # FP32 rounding of values below I
+        bad = d.copy()
+        bad[3, 1] = np.nan
+        assert lib.fcc_doa_table(p._h, bad.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), d.shape[0],
+                                 tab.ctypes.data_as(ctypes.c_void_p)) == -1
