@@ -120,6 +120,54 @@ def cpu_baseline(rec, tau_max, D, budget_s):
                       f"one thread, {dt:.1f} s"}
 
 
+def other_paths(torch, fcc, rec, x, dev, args):
+    """Throughput of the extended paths on the same recording: recursive
+    smoothing (alpha = 0.1, FP32, r = 2 grid), the learned sub-sample stage
+    (untrained weights: the cost is the same) and the DoA search."""
+    import numpy as np
+    from paper_2204_13622_amd import learned
+    out = {}
+    steps = args.steps
+    sm = fcc.Plan(rec.mic_xyz, rec.fs, rec.c, frame_size=rec.N, hop=rec.hop, rank=11, interp=2, alpha=0.1)
+    T = sm.num_frames(rec.L)
+    ws = torch.empty(sm.workspace_bytes(T), dtype=torch.uint8, device=dev)
+    o = torch.empty((T, sm.P), dtype=torch.int32, device=dev)
+    f = lambda: sm.tdoa(x, out=o, workspace=ws)  # noqa: E731
+    for _ in range(args.warmup):
+        f()
+    ms = time_loop(torch, f, steps)
+    out["smoothed_alpha0.1_r2_fp32_D11"] = {"ms": round(ms, 4), "pair_frames_per_s": round(T * sm.P / (ms * 1e-3))}
+
+    lp = fcc.Plan(rec.mic_xyz, rec.fs, rec.c, frame_size=rec.N, hop=rec.hop, rank=11, precision="fp16")
+    T = lp.num_frames(rec.L)
+    spec = lp.spectra(x)
+    net = learned.Mlp(2 * lp.rank, 128, seed=1, device=dev)
+    tau = torch.empty((T, lp.P), dtype=torch.float32, device=dev)
+    conf = torch.empty_like(tau)
+    lws = torch.empty(learned.learned_workspace_bytes(lp, 128, T), dtype=torch.uint8, device=dev)
+    f = lambda: learned.tdoa_learned(lp, spec, net, 1.0, tau=tau, confidence=conf, workspace=lws)  # noqa: E731
+    for _ in range(2):
+        f()
+    ms = time_loop(torch, f, max(3, steps // 10))
+    out["learned_from_spectra_fp16_D11_H128"] = {"ms": round(ms, 4), "pair_frames_per_s": round(T * lp.P / (ms * 1e-3))}
+
+    G = 1024
+    k = np.arange(G) + 0.5
+    z = 1.0 - k / G
+    phi = np.pi * (3.0 - np.sqrt(5.0)) * k
+    dirs = np.stack([np.sqrt(1 - z * z) * np.cos(phi), np.sqrt(1 - z * z) * np.sin(phi), z], 1)
+    table = lp.doa_table(dirs, dev)
+    y = lp.correlation(spec)
+    d = torch.empty(T, dtype=torch.int32, device=dev)
+    f = lambda: lp.doa(y, table)  # noqa: E731
+    for _ in range(2):
+        f()
+    ms = time_loop(torch, f, max(3, steps // 10))
+    out["doa_search_G1024_upper_hemisphere"] = {"ms": round(ms, 4), "frames_per_s": round(T / (ms * 1e-3))}
+    del d
+    return out
+
+
 def main():
     args = parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -169,7 +217,8 @@ def main():
     dom = "pair" if ms_pair >= ms_stft else "stft_phat"
     dom_ms = ms_pair if dom == "pair" else ms_stft
     achieved = kb[dom] / (dom_ms * 1e-3) / 1e9
-    pair_file = "pair_valu.hip" if args.precision == "fp32" else "pair_mfma.hip"
+    # the pair kernel the library dispatches for this configuration
+    pair_file = "pair_fold32.hip" if args.precision == "fp32" else "pair_mfma.hip"
     traffic = traffic_for(pair_file if dom == "pair" else "stft_phat.hip", workload,
                           args.precision, args.rank)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
@@ -179,7 +228,7 @@ def main():
                 "kernels_GBs": {"stft_phat": round(kb["stft_phat"] / ms_stft / 1e6, 1),
                                 "pair": round(kb["pair"] / ms_pair / 1e6, 1)}}
 
-    sweep = []
+    sweep, extras = [], {}
     if not args.no_sweep:
         for prec, rank, method in [("fp32", 6, "fcc"), ("fp32", 11, "fcc"), ("bf16", 6, "fcc"),
                                    ("bf16", 11, "fcc"), ("fp16", 6, "fcc"), ("fp16", 11, "fcc"),
@@ -187,10 +236,12 @@ def main():
                                    ("fp16", 0, "gcc")]:
             pl, Tq, wq, oq = make(prec, rank, method)
             f = lambda: pl.tdoa(x, out=oq, workspace=wq)  # noqa: E731
-            f()
-            msq = time_loop(torch, f, max(5, args.steps // 5))
+            for _ in range(args.warmup):
+                f()
+            msq = time_loop(torch, f, args.steps)
             sweep.append({"method": method, "precision": prec, "rank": pl.rank,
                           "ms": round(msq, 4), "pair_frames_per_s": round(Tq * pl.P / (msq * 1e-3))})
+        extras = other_paths(torch, fcc, rec, x, dev, args)
 
     cpu = None
     if not args.no_cpu:
@@ -209,6 +260,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "sweep": sweep,
+        "other_paths": extras,
     }
     print(json.dumps(line), flush=True)
 
