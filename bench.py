@@ -30,7 +30,7 @@ def parse_args():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--precision", default="fp16", choices=["fp32", "bf16", "fp16", "fp8"])
     ap.add_argument("--rank", type=int, default=11)
     ap.add_argument("--no-sweep", action="store_true", help="skip the precision/rank/method sweep")

@@ -75,6 +75,11 @@ __device__ __forceinline__ void wave_sync() {
 
 constexpr int kPrefetch = 16;   // rounds of 16-byte chunks per lane in flight (16 KB per wavefront)
 
+// 32-bit words of LDS shared by the workgroup: basis rows, G, pair list
+__host__ __device__ __forceinline__ int shared_words(int Dp, int NH, int TT, int P) {
+  return Dp * (NH + 4) + 16 * TT * Dp + P;
+}
+
 template <class S, int KB, int TT, bool WRITE_Y, int kWaves>
 __global__ __launch_bounds__(64 * kWaves, 2) void pair_mfma_kernel(
     const typename S::T* __restrict__ spec, int64_t T, int M, int P, int NH, int I, int lag0,
@@ -90,22 +95,22 @@ __global__ __launch_bounds__(64 * kWaves, 2) void pair_mfma_kernel(
   // over the LDS banks) and, after the projection, the lag rows Y
   // basis rows are NH + 4 words apart so the four rows a wavefront reads at
   // once fall on different LDS banks
+  // The dictionary G and the pair list also sit in LDS: inside the frame loop
+  // the only global loads are the next frame's prefetch, so no wait on the
+  // in-order load counter ever has to drain that prefetch early.
   const int prow_words = NH + 4;
   uint32_t* ptab = lds_all;
-  uint32_t* slab = lds_all + Dp * prow_words + wave * slab_words;
+  float* gsh = reinterpret_cast<float*>(ptab + Dp * prow_words);        // [16 TT][Dp]
+  uint32_t* psh = ptab + Dp * prow_words + 16 * TT * Dp;                // [P] = i | j << 8
+  uint32_t* slab = lds_all + ((shared_words(Dp, NH, TT, P) + 3) & ~3) + wave * slab_words;   // 16-byte aligned
   float* ybuf = reinterpret_cast<float*>(slab);
   const int row = NH + 4;
   for (int c = threadIdx.x; c < Dp * NH / 4; c += 64 * kWaves) {
     const int k = c / (NH / 4), q = c - k * (NH / 4);
     *reinterpret_cast<uint4*>(ptab + k * prow_words + 4 * q) = reinterpret_cast<const uint4*>(prow16)[c];
   }
-
-  // A operands of the expansion: G(tau = 16 tt + col, k = 4 kb + g)
-  float gx[TT][KB];
-#pragma unroll
-  for (int tt = 0; tt < TT; ++tt)
-#pragma unroll
-    for (int kb = 0; kb < KB; ++kb) gx[tt][kb] = gexp[(16 * tt + col) * Dp + 4 * kb + g];
+  for (int c = threadIdx.x; c < 16 * TT * Dp; c += 64 * kWaves) gsh[c] = gexp[c];
+  for (int c = threadIdx.x; c < P; c += 64 * kWaves) psh[c] = pairs[2 * c] | (uint32_t(pairs[2 * c + 1]) << 8);
   __syncthreads();
 
   // a frame is M * NH / 4 chunks of 16 bytes (4 slots); chunk c is slots
@@ -132,12 +137,21 @@ __global__ __launch_bounds__(64 * kWaves, 2) void pair_mfma_kernel(
   for (; t < T; t += stride) {
     // ---- stage the frame into the slab --------------------------------------
     const typename S::T* base = spec + t * (int64_t)M * NH;
+    if (rounds >= kPrefetch) {                  // every prefetch slot holds data: no guards
 #pragma unroll
-    for (int u = 0; u < kPrefetch; ++u) {
-      if (u < rounds) {
+      for (int u = 0; u < kPrefetch; ++u) {
         const int c = lane + 64 * u;
         const int mic = c >> lg_row, q = c & ((NH / 4) - 1);
         *reinterpret_cast<uint4*>(slab + mic * row + 4 * q) = pre[u];
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < kPrefetch; ++u) {
+        if (u < rounds) {
+          const int c = lane + 64 * u;
+          const int mic = c >> lg_row, q = c & ((NH / 4) - 1);
+          *reinterpret_cast<uint4*>(slab + mic * row + 4 * q) = pre[u];
+        }
       }
     }
     for (int c = lane + 64 * (rounds < kPrefetch ? rounds : kPrefetch); c < chunks; c += 64) {
@@ -189,6 +203,12 @@ __global__ __launch_bounds__(64 * kWaves, 2) void pair_mfma_kernel(
     wave_sync();   // every lane has read the spectra; the slab now takes Y
 
     // ---- expansion: Y_i(tau, j) = sum_k G(tau, k) H_k(i, j) --------------------
+    // A operands: G(tau = 16 tt + col, k = 4 kb + g)
+    float gx[TT][KB];
+#pragma unroll
+    for (int tt = 0; tt < TT; ++tt)
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) gx[tt][kb] = gsh[(16 * tt + col) * Dp + 4 * kb + g];
 #pragma unroll
     for (int ib = 0; ib < 4; ++ib) {
 #pragma unroll
@@ -212,7 +232,8 @@ __global__ __launch_bounds__(64 * kWaves, 2) void pair_mfma_kernel(
 
     // ---- per pair: y_ij(tau) = Y_i(tau, j) + Y_j(-tau, i); first-index argmax
     for (int p = lane; p < P; p += 64) {
-      const int i = pairs[2 * p], j = pairs[2 * p + 1];
+      const uint32_t ij = psh[p];
+      const int i = ij & 0xff, j = ij >> 8;
       const int64_t orow = t * P + p;
       const float* ya = ybuf + i * kYRow + j;
       const float* yb = ybuf + (I - 1) * kYStride + j * kYRow + i;
@@ -240,8 +261,12 @@ int slab_words(const PairArgs& a) {
   return spec_words > y_words ? spec_words : y_words;
 }
 
+int lag_tiles(const PairArgs& a) { return a.I <= 16 ? 1 : (a.I <= 32 ? 2 : 3); }
+
 size_t lds_bytes(const PairArgs& a, int waves) {
-  return sizeof(uint32_t) * (size_t(a.Dpad) * (a.N / 2 + 4) + size_t(waves) * slab_words(a));
+  // slabs hold uint4 rows: keep them 16-byte aligned
+  const size_t head = (size_t(shared_words(a.Dpad, a.N / 2, lag_tiles(a), a.P)) + 3) & ~size_t(3);
+  return sizeof(uint32_t) * (head + size_t(waves) * slab_words(a));
 }
 
 // wavefronts per block: four when the block's LDS fits, else two
