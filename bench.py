@@ -37,6 +37,8 @@ def parse_args():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--seed", type=int, default=2000)
+    ap.add_argument("--batch-seconds", type=float, default=2.0,
+                    help="audio per array in the 256-array batch measurement")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run plain device copies of this many MiB (counter calibration)")
     return ap.parse_args()
@@ -165,6 +167,31 @@ def other_paths(torch, fcc, rec, x, dev, args):
     ms = time_loop(torch, f, max(3, steps // 10))
     out["doa_search_G1024_upper_hemisphere"] = {"ms": round(ms, 4), "frames_per_s": round(T / (ms * 1e-3))}
     del d
+
+    # batches: 256 independent arrays (M 2..16, aperture 2-10 cm, f_S 16 / 48 kHz,
+    # N 256 / 512 / 1024, rank tau_max + 1), one graph per pass, autotuned
+    from gen import batch_arrays
+    arrays = batch_arrays(4000, 256, args.batch_seconds)
+    plans = []
+    for a in arrays:
+        p0 = fcc.Plan(a["xyz"], a["fs"], frame_size=a["N"], hop=a["hop"], precision="fp16")
+        plans.append(fcc.Plan(a["xyz"], a["fs"], frame_size=a["N"], hop=a["hop"], rank=p0.tau_max + 1,
+                              precision="fp16"))
+    b = fcc.Batch(plans, [a["x"].shape[1] for a in arrays], device=dev)
+    audio = b.pack([torch.from_numpy(a["x"]) for a in arrays])
+    del arrays
+    units = sum(T * p.P for T, p in zip(b.frames, plans))
+    tuning = b.tune(audio)
+    for graph in (True, False):
+        f = lambda: b.tdoa(audio, graph=graph)  # noqa: E731
+        for _ in range(3):
+            f()
+        ms = time_loop(torch, f, max(5, steps // 5))
+        out["batch_256_arrays_graph" if graph else "batch_256_arrays_eager"] = {
+            "ms": round(ms, 4), "pair_frames_per_s": round(units / (ms * 1e-3)), "pair_frames": units,
+            "seconds_per_array": args.batch_seconds, "classes": b.info.num_classes}
+    out["batch_tuning"] = tuning
+    b.close()
     return out
 
 

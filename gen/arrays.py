@@ -299,3 +299,39 @@ def sphere_grid(G: int, upper: bool = False) -> np.ndarray:
     rho = np.sqrt(np.maximum(0.0, 1.0 - z * z))
     phi = np.pi * (3.0 - np.sqrt(5.0)) * k
     return np.stack([rho * np.cos(phi), rho * np.sin(phi), z], axis=1)
+
+
+def random_planar_array(rng, M: int, aperture: float) -> np.ndarray:
+    """M microphones uniformly in a disc, rescaled so that the largest
+    distance between two of them is `aperture` metres; [M][3], z = 0."""
+    r = np.sqrt(rng.uniform(0.0, 1.0, M))
+    phi = rng.uniform(0.0, 2.0 * np.pi, M)
+    xy = np.stack([r * np.cos(phi), r * np.sin(phi)], axis=1)
+    d = np.sqrt(((xy[:, None, :] - xy[None, :, :]) ** 2).sum(-1)).max()
+    xy *= aperture / d
+    return np.concatenate([xy, np.zeros((M, 1))], axis=1)
+
+
+def batch_arrays(seed: int, count: int, seconds: float):
+    """`count` independent arrays: M uniform in {2..16} on random planar layouts
+    of 2-10 cm aperture, f_S in {16, 48} kHz, N in {256, 512, 1024} with hop N/4,
+    each hearing an AR(2) source from a random azimuth (integer delays) with
+    sensor noise at an SNR uniform in [0, 20] dB.  Returns a list of dicts with
+    xyz, fs, N, hop and x [M][L] float32."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(count):
+        M = int(rng.integers(2, 17))
+        xyz = random_planar_array(rng, M, rng.uniform(0.02, 0.10))
+        fs = float(rng.choice([16000.0, 48000.0]))
+        N = int(rng.choice([256, 512, 1024]))
+        L = int(round(seconds * fs))
+        az = rng.uniform(0.0, 2.0 * np.pi)
+        delays = np.rint(far_field_delays(xyz, az, fs, 343.0)).astype(np.int64)
+        pad = int(np.abs(delays).max()) + 8
+        s = _ar2(rng, L + 2 * pad, 0.95, rng.uniform(0.05 * np.pi, 0.45 * np.pi) * (16000.0 / fs))
+        x = np.stack([_integer_delay(s, int(d), L, pad) for d in delays])
+        snr = rng.uniform(0.0, 20.0, M)
+        x = x + np.stack([_snr_noise(rng, x[m], snr[m]) for m in range(M)])
+        out.append({"xyz": xyz, "fs": fs, "N": N, "hop": N // 4, "x": x.astype(np.float32)})
+    return out

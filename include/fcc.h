@@ -245,6 +245,52 @@ fcc_status fcc_doa_table(fcc_plan plan, const double* dirs, int32_t num_dirs, fl
 fcc_status fcc_doa(fcc_plan plan, const float* d_y, int64_t num_frames, const float* d_table, int32_t num_dirs,
                    int32_t* d_doa, float* d_score, hipStream_t stream);
 
+/* ---- batches of independent arrays ------------------------------------------
+ * Many arrays of uneven microphone count, aperture, sample rate, frame size and
+ * rank (each with its own plan) in one pass: every array's front end in one
+ * persistent launch, and the pair stage of every array in one persistent
+ * launch per class of arrays sharing a matrix-core tile shape, with work items
+ * (array, block of transforms) and (array, tile of frames) taken from queues.
+ * With use_graph the pass is captured once into a graph (per set of buffer
+ * pointers) and replayed.  fcc_batch_tune times candidate tile shapes on the
+ * given buffers and keeps the fastest.
+ * Limits: every plan FP16 or BF16 storage (the same), method FCC, alpha = 1,
+ * M <= 16, N >= 32, I <= 48, rank <= 32 (FCC_ERR_UNSUPPORTED otherwise).
+ * Plans are copied; num_samples[a] fixes array a's length L_a at creation.
+ * Buffers (caller-owned, device):
+ *   d_image     info.image_bytes, 256-byte aligned, filled by fcc_batch_upload;
+ *   d_audio     info.audio_floats FP32: array a's [M_a][L_a] block (row stride
+ *               L_a) at offset audio_offset[a] (fcc_batch_layout);
+ *   d_tdoa      info.tdoa_count int32: array a's [T_a][P_a] lags (units of 1/r
+ *               sample) at offset tdoa_offset[a];
+ *   d_workspace info.workspace_bytes, 256-byte aligned (spectra and queues).
+ * A batch object is not thread-safe (tuning and the graph cache mutate it);
+ * calls that share a workspace must be ordered. */
+typedef struct fcc_batch_s* fcc_batch;
+typedef struct {
+  int32_t num_arrays;
+  int32_t num_classes;            /* pair-stage launches per pass             */
+  size_t image_bytes;
+  size_t workspace_bytes;
+  int64_t audio_floats;
+  int64_t tdoa_count;
+} fcc_batch_info;
+fcc_status fcc_batch_create(const fcc_plan* plans, int32_t num_arrays, const int64_t* num_samples, fcc_batch* out);
+void fcc_batch_destroy(fcc_batch batch);
+fcc_status fcc_batch_query(fcc_batch batch, fcc_batch_info* info);
+/* Host arrays of num_arrays entries; any may be NULL. */
+fcc_status fcc_batch_layout(fcc_batch batch, int64_t* audio_offset, int64_t* tdoa_offset, int64_t* num_frames);
+fcc_status fcc_batch_upload(fcc_batch batch, void* d_image, hipStream_t stream);
+fcc_status fcc_batch_tdoa(fcc_batch batch, const void* d_image, const float* d_audio, int32_t* d_tdoa,
+                          void* d_workspace, int32_t use_graph, hipStream_t stream);
+/* Autotuner; synchronises `stream` while timing.  Overwrites d_tdoa. */
+fcc_status fcc_batch_tune(fcc_batch batch, const void* d_image, const float* d_audio, int32_t* d_tdoa,
+                          void* d_workspace, hipStream_t stream);
+/* The tile shapes in use: values[0..1] front end (items per queue grab,
+ * workgroups per compute unit), then per class (frames per item, wavefronts
+ * per workgroup, workgroups per compute unit); capacity >= 2 + 3 num_classes. */
+fcc_status fcc_batch_tuning(fcc_batch batch, int32_t* values, int32_t capacity);
+
 /* ---- learned sub-sample TDoA ------------------------------------------------
  * Not from the paper: a multilayer perceptron refining the FCC lag of one
  * pair-frame from its projection coefficients (fcc_coefficients).  One row =

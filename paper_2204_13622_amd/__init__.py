@@ -348,3 +348,8 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+from .batch import Batch  # noqa: E402,F401
+
+__all__.append("Batch")

@@ -20,6 +20,8 @@ EXPORTS = ("fcc_plan_create", "fcc_plan_destroy", "fcc_plan_query", "fcc_plan_up
            "fcc_basis_export", "fcc_mlp_num_params", "fcc_mlp_workspace_bytes", "fcc_mlp_forward",
            "fcc_mlp_backward", "fcc_mlp_adam", "fcc_learned_workspace_bytes", "fcc_tdoa_learned",
            "fcc_smooth_workspace_bytes", "fcc_tdoa_smoothed", "fcc_doa_table", "fcc_doa",
+           "fcc_batch_create", "fcc_batch_destroy", "fcc_batch_query", "fcc_batch_layout", "fcc_batch_upload",
+           "fcc_batch_tdoa", "fcc_batch_tune", "fcc_batch_tuning",
            "fcc_status_string", "fcc_last_error")
 
 
@@ -37,6 +39,12 @@ class FccConfig(ctypes.Structure):
                 ("tau_max", ctypes.c_int32), ("rank", ctypes.c_int32),
                 ("interp", ctypes.c_int32), ("alpha", ctypes.c_float),
                 ("precision", ctypes.c_int32), ("method", ctypes.c_int32)]
+
+
+class FccBatchInfo(ctypes.Structure):
+    _fields_ = [("num_arrays", ctypes.c_int32), ("num_classes", ctypes.c_int32),
+                ("image_bytes", ctypes.c_size_t), ("workspace_bytes", ctypes.c_size_t),
+                ("audio_floats", ctypes.c_int64), ("tdoa_count", ctypes.c_int64)]
 
 
 class FccPlanInfo(ctypes.Structure):
@@ -86,6 +94,13 @@ def load() -> ctypes.CDLL:
         "fcc_mlp_workspace_bytes": [ctypes.c_int32, ctypes.c_int32, i64, ctypes.POINTER(ctypes.c_size_t)],
         "fcc_mlp_forward": [vp, ctypes.c_int32, ctypes.c_int32, vp, i64, vp, vp, vp],
         "fcc_mlp_backward": [vp, ctypes.c_int32, ctypes.c_int32, vp, vp, i64, vp, vp, vp, vp, vp],
+        "fcc_batch_create": [ctypes.POINTER(vp), ctypes.c_int32, ctypes.POINTER(i64), ctypes.POINTER(vp)],
+        "fcc_batch_query": [vp, ctypes.POINTER(FccBatchInfo)],
+        "fcc_batch_layout": [vp, ctypes.POINTER(i64), ctypes.POINTER(i64), ctypes.POINTER(i64)],
+        "fcc_batch_upload": [vp, vp, vp],
+        "fcc_batch_tdoa": [vp, vp, vp, vp, vp, ctypes.c_int32, vp],
+        "fcc_batch_tune": [vp, vp, vp, vp, vp, vp],
+        "fcc_batch_tuning": [vp, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32],
         "fcc_doa_table": [vp, dp, ctypes.c_int32, vp],
         "fcc_doa": [vp, vp, i64, vp, ctypes.c_int32, vp, vp, vp],
         "fcc_smooth_workspace_bytes": [vp, i64, ctypes.POINTER(ctypes.c_size_t)],
@@ -101,6 +116,8 @@ def load() -> ctypes.CDLL:
         fn.restype = ctypes.c_int
     lib.fcc_mlp_num_params.argtypes = [ctypes.c_int32, ctypes.c_int32]
     lib.fcc_mlp_num_params.restype = ctypes.c_size_t
+    lib.fcc_batch_destroy.argtypes = [vp]
+    lib.fcc_batch_destroy.restype = None
     lib.fcc_plan_destroy.argtypes = [vp]
     lib.fcc_plan_destroy.restype = None
     lib.fcc_status_string.argtypes = [ctypes.c_int]

@@ -4,6 +4,8 @@
 
 #include <cstdint>
 #include <cstring>
+#include <algorithm>
+#include <map>
 #include <new>
 #include <string>
 
@@ -13,6 +15,27 @@
 
 struct fcc_plan_s {
   fcc::Plan p;
+};
+
+// A batch of independent arrays: copies of their plans, the layout of their
+// inputs and outputs, the work classes, the tuned tile shapes and the cached
+// graph of one pass.
+struct fcc_batch_s {
+  std::vector<fcc::Plan> plans;
+  std::vector<fcc::BatchArray> arrays;
+  std::vector<int32_t> members;
+  std::vector<fcc::BatchClass> classes;
+  std::vector<unsigned char> image;
+  size_t arrays_off = 0, members_off = 0;
+  int64_t audio_floats = 0, tdoa_count = 0, stft_items = 0;
+  size_t spec_bytes = 0, queue_off = 0, workspace_bytes = 0;
+  std::vector<int> sizes;
+  fcc_precision precision = FCC_FP16;
+  fcc::StftTuning stft_tuning;
+  std::vector<fcc::PairTuning> pair_tuning;
+  hipStream_t capture_stream = nullptr;
+  hipGraphExec_t exec = nullptr;
+  const void* graph_key[4] = {nullptr, nullptr, nullptr, nullptr};
 };
 
 namespace {
@@ -520,6 +543,290 @@ fcc_status fcc_doa(fcc_plan plan, const float* d_y, int64_t num_frames, const fl
   a.stream = stream;
   if (!fcc::doa_supported(a)) return set_error(FCC_ERR_UNSUPPORTED, "one frame's correlations exceed 48 KB");
   return hip_status(fcc::launch_doa(a), "doa launch");
+}
+
+// ---- batches ---------------------------------------------------------------
+
+namespace {
+
+size_t batch_align(size_t b) { return (b + 255) & ~size_t(255); }
+
+void batch_drop_graph(fcc_batch b) {
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  b->exec = nullptr;
+  for (auto& k : b->graph_key) k = nullptr;
+}
+
+fcc::BatchRun batch_run(fcc_batch b, const void* d_image, const float* d_audio, int32_t* d_tdoa, void* d_ws,
+                        hipStream_t stream) {
+  fcc::BatchRun r{};
+  const unsigned char* img = static_cast<const unsigned char*>(d_image);
+  r.arrays = reinterpret_cast<const fcc::BatchArray*>(img + b->arrays_off);
+  r.n_arrays = int(b->arrays.size());
+  r.members = reinterpret_cast<const int32_t*>(img + b->members_off);
+  r.image = img;
+  r.audio = d_audio;
+  r.spec = static_cast<unsigned char*>(d_ws);
+  r.tdoa = d_tdoa;
+  r.queue = reinterpret_cast<int*>(static_cast<unsigned char*>(d_ws) + b->queue_off);
+  r.stft_items = b->stft_items;
+  r.sizes = b->sizes;
+  r.precision = b->precision;
+  r.stream = stream;
+  return r;
+}
+
+hipError_t batch_enqueue(fcc_batch b, const fcc::BatchRun& r) {
+  hipError_t e = fcc::launch_fill_zero(reinterpret_cast<float*>(r.queue), int64_t(1 + b->classes.size()), r.stream);
+  if (e != hipSuccess) return e;
+  if ((e = fcc::launch_batch_stft(r, b->stft_tuning)) != hipSuccess) return e;
+  for (size_t c = 0; c < b->classes.size(); ++c)
+    if ((e = fcc::launch_batch_pair(r, b->classes[c], b->pair_tuning[c])) != hipSuccess) return e;
+  return hipSuccess;
+}
+
+fcc_status batch_check(fcc_batch b, const void* d_image, const float* d_audio, int32_t* d_tdoa, void* d_ws) {
+  if (!b) return set_error(FCC_ERR_INVALID_ARG, "NULL batch");
+  if (!d_image || !d_ws || (b->audio_floats > 0 && !d_audio) || (b->tdoa_count > 0 && !d_tdoa))
+    return set_error(FCC_ERR_INVALID_ARG, "NULL pointer");
+  if (!aligned(d_image, 256) || !aligned(d_ws, 256) || !aligned(d_audio, 4) || !aligned(d_tdoa, 4))
+    return set_error(FCC_ERR_INVALID_ARG, "d_image and d_workspace must be 256-byte aligned");
+  return FCC_OK;
+}
+
+}  // namespace
+
+fcc_status fcc_batch_create(const fcc_plan* plans, int32_t num_arrays, const int64_t* num_samples, fcc_batch* out) {
+  if (!plans || !num_samples || !out || num_arrays < 1)
+    return set_error(FCC_ERR_INVALID_ARG, "plans, num_samples and out must be non-NULL, num_arrays >= 1");
+  *out = nullptr;
+  fcc_batch b = new (std::nothrow) fcc_batch_s;
+  if (!b) return set_error(FCC_ERR_INTERNAL, "out of host memory");
+  auto fail = [&](fcc_status st, const char* msg) {
+    delete b;
+    return set_error(st, msg);
+  };
+  b->precision = plans[0] ? plans[0]->p.precision : FCC_FP16;
+  std::map<std::pair<int, int>, std::vector<int>> by_shape;
+  size_t img = 0, spec = 0;
+  for (int a = 0; a < num_arrays; ++a) {
+    if (!plans[a]) return fail(FCC_ERR_INVALID_ARG, "NULL plan");
+    const fcc::Plan& p = plans[a]->p;
+    if (num_samples[a] < 0) return fail(FCC_ERR_INVALID_ARG, "num_samples must be >= 0");
+    if (p.precision != b->precision) return fail(FCC_ERR_INVALID_ARG, "every plan of a batch has the same precision");
+    if (p.precision != FCC_FP16 && p.precision != FCC_BF16)
+      return fail(FCC_ERR_UNSUPPORTED, "batches are built for FP16 or BF16 spectra");
+    if (p.method != FCC_METHOD_FCC || p.alpha < 1.0f)
+      return fail(FCC_ERR_UNSUPPORTED, "batches run the FCC method without smoothing");
+    const int kb = p.Dpad / 4, tt = p.I <= 16 ? 1 : (p.I <= 32 ? 2 : 3);
+    if (p.M > 16 || p.N < 32 || p.I > 48 || !(kb == 1 || kb == 2 || kb == 3 || kb == 4 || kb == 6 || kb == 8))
+      return fail(FCC_ERR_UNSUPPORTED, "an array is outside the matrix-core pair stage (M <= 16, N >= 32, I <= 48, rank <= 32)");
+    b->plans.push_back(p);
+    fcc::BatchArray d{};
+    d.M = p.M;
+    d.P = p.P;
+    d.N = p.N;
+    d.hop = p.hop;
+    d.I = p.I;
+    d.lag0 = p.r * p.tau_max;
+    d.L = num_samples[a];
+    d.T = frames_of(p, num_samples[a]);
+    d.audio_off = b->audio_floats;
+    d.spec_off = int64_t(spec);
+    d.tdoa_off = b->tdoa_count;
+    d.img_off = int64_t(img);
+    d.tab_twiddle = int64_t(p.layout.twiddle);
+    d.tab_pairs = int64_t(p.layout.pairs);
+    d.tab_prow16 = int64_t(p.layout.prow16);
+    d.tab_gexp = int64_t(p.layout.gexp);
+    d.stft_first = b->stft_items;
+    const int fpb = fcc::stft_transforms_per_block(p.N);
+    b->stft_items += (d.T * d.M + fpb - 1) / fpb;
+    b->audio_floats += int64_t(p.M) * num_samples[a];
+    b->tdoa_count += d.T * p.P;
+    spec += batch_align(size_t(d.T) * p.M * (p.N / 2) * p.spec_elem);
+    img += batch_align(p.layout.total);
+    b->arrays.push_back(d);
+    by_shape[{kb, tt}].push_back(a);
+    if (std::find(b->sizes.begin(), b->sizes.end(), p.N) == b->sizes.end()) b->sizes.push_back(p.N);
+  }
+  for (auto& kv : by_shape) {
+    fcc::BatchClass c;
+    c.index = int(b->classes.size());
+    c.kb = kv.first.first;
+    c.tt = kv.first.second;
+    c.member_first = int(b->members.size());
+    c.member_count = int(kv.second.size());
+    for (int a : kv.second) {
+      const fcc::BatchArray& d = b->arrays[a];
+      b->members.push_back(a);
+      c.member_frames.push_back(d.T);
+      c.head_words_max = std::max(c.head_words_max, fcc::batch_head_words(4 * c.kb, d.N / 2, c.tt, d.P));
+      c.slab_words_max = std::max(c.slab_words_max, fcc::batch_slab_words(d.N, d.I));
+    }
+    b->classes.push_back(c);
+  }
+  b->pair_tuning.assign(b->classes.size(), fcc::PairTuning{});
+  b->arrays_off = img;
+  b->members_off = batch_align(b->arrays_off + sizeof(fcc::BatchArray) * b->arrays.size());
+  b->image.assign(batch_align(b->members_off + sizeof(int32_t) * b->members.size()), 0);
+  for (int a = 0; a < num_arrays; ++a)
+    std::memcpy(b->image.data() + b->arrays[a].img_off, b->plans[a].image.data(), b->plans[a].image.size());
+  std::memcpy(b->image.data() + b->arrays_off, b->arrays.data(), sizeof(fcc::BatchArray) * b->arrays.size());
+  std::memcpy(b->image.data() + b->members_off, b->members.data(), sizeof(int32_t) * b->members.size());
+  b->spec_bytes = spec;
+  b->queue_off = batch_align(spec);
+  b->workspace_bytes = b->queue_off + 256;
+  if (b->classes.size() + 1 > 64) return fail(FCC_ERR_UNSUPPORTED, "too many tile classes in one batch");
+  *out = b;
+  return FCC_OK;
+}
+
+void fcc_batch_destroy(fcc_batch b) {
+  if (!b) return;
+  batch_drop_graph(b);
+  if (b->capture_stream) hipStreamDestroy(b->capture_stream);
+  delete b;
+}
+
+fcc_status fcc_batch_query(fcc_batch b, fcc_batch_info* info) {
+  if (!b || !info) return set_error(FCC_ERR_INVALID_ARG, "NULL argument");
+  info->num_arrays = int32_t(b->arrays.size());
+  info->num_classes = int32_t(b->classes.size());
+  info->image_bytes = b->image.size();
+  info->workspace_bytes = b->workspace_bytes;
+  info->audio_floats = b->audio_floats;
+  info->tdoa_count = b->tdoa_count;
+  return FCC_OK;
+}
+
+fcc_status fcc_batch_layout(fcc_batch b, int64_t* audio_offset, int64_t* tdoa_offset, int64_t* num_frames) {
+  if (!b) return set_error(FCC_ERR_INVALID_ARG, "NULL batch");
+  for (size_t a = 0; a < b->arrays.size(); ++a) {
+    if (audio_offset) audio_offset[a] = b->arrays[a].audio_off;
+    if (tdoa_offset) tdoa_offset[a] = b->arrays[a].tdoa_off;
+    if (num_frames) num_frames[a] = b->arrays[a].T;
+  }
+  return FCC_OK;
+}
+
+fcc_status fcc_batch_upload(fcc_batch b, void* d_image, hipStream_t stream) {
+  if (!b || !d_image) return set_error(FCC_ERR_INVALID_ARG, "NULL argument");
+  if (!aligned(d_image, 256)) return set_error(FCC_ERR_INVALID_ARG, "d_image must be 256-byte aligned");
+  return hip_status(hipMemcpyAsync(d_image, b->image.data(), b->image.size(), hipMemcpyHostToDevice, stream),
+                    "batch image copy");
+}
+
+fcc_status fcc_batch_tdoa(fcc_batch b, const void* d_image, const float* d_audio, int32_t* d_tdoa, void* d_workspace,
+                          int32_t use_graph, hipStream_t stream) {
+  fcc_status st = batch_check(b, d_image, d_audio, d_tdoa, d_workspace);
+  if (st != FCC_OK) return st;
+  if (!use_graph)
+    return hip_status(batch_enqueue(b, batch_run(b, d_image, d_audio, d_tdoa, d_workspace, stream)), "batch launch");
+  const void* key[4] = {d_image, d_audio, d_tdoa, d_workspace};
+  if (!b->exec || !std::equal(key, key + 4, b->graph_key)) {
+    batch_drop_graph(b);
+    if (!b->capture_stream &&
+        hipStreamCreateWithFlags(&b->capture_stream, hipStreamNonBlocking) != hipSuccess)
+      return set_error(FCC_ERR_HIP, "capture stream creation failed");
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamBeginCapture(b->capture_stream, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) return hip_status(e, "graph capture begin");
+    const hipError_t le = batch_enqueue(b, batch_run(b, d_image, d_audio, d_tdoa, d_workspace, b->capture_stream));
+    e = hipStreamEndCapture(b->capture_stream, &graph);
+    if (le != hipSuccess) {
+      if (graph) hipGraphDestroy(graph);
+      return hip_status(le, "batch launch during capture");
+    }
+    if (e != hipSuccess) return hip_status(e, "graph capture end");
+    e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+    hipGraphDestroy(graph);
+    if (e != hipSuccess) {
+      b->exec = nullptr;
+      return hip_status(e, "graph instantiation");
+    }
+    std::copy(key, key + 4, b->graph_key);
+  }
+  return hip_status(hipGraphLaunch(b->exec, stream), "graph launch");
+}
+
+fcc_status fcc_batch_tune(fcc_batch b, const void* d_image, const float* d_audio, int32_t* d_tdoa, void* d_workspace,
+                          hipStream_t stream) {
+  fcc_status st = batch_check(b, d_image, d_audio, d_tdoa, d_workspace);
+  if (st != FCC_OK) return st;
+  batch_drop_graph(b);
+  const fcc::BatchRun r = batch_run(b, d_image, d_audio, d_tdoa, d_workspace, stream);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return set_error(FCC_ERR_HIP, "event creation failed");
+  if (hipEventCreate(&e1) != hipSuccess) {
+    hipEventDestroy(e0);
+    return set_error(FCC_ERR_HIP, "event creation failed");
+  }
+  const int reps = 3;
+  // time `launch` (queues cleared first) reps times; +inf when it cannot run
+  auto time_of = [&](auto&& launch) -> float {
+    hipError_t e = hipSuccess;
+    for (int w = 0; w < 1 + reps && e == hipSuccess; ++w) {
+      if (w == 1) hipEventRecord(e0, stream);
+      e = fcc::launch_fill_zero(reinterpret_cast<float*>(r.queue), int64_t(1 + b->classes.size()), stream);
+      if (e == hipSuccess) e = launch();
+    }
+    hipEventRecord(e1, stream);
+    if (hipEventSynchronize(e1) != hipSuccess || e != hipSuccess) return 3.4e38f;
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, e0, e1);
+    return ms;
+  };
+  fcc_status result = FCC_OK;
+  float best = 3.4e38f;
+  fcc::StftTuning best_s = b->stft_tuning;
+  for (int chunk : {1, 2, 4, 8, 16})
+    for (int bpc : {2, 3, 4}) {
+      const fcc::StftTuning t{chunk, bpc};
+      const float ms = time_of([&] { return fcc::launch_batch_stft(r, t); });
+      if (ms < best) {
+        best = ms;
+        best_s = t;
+      }
+    }
+  if (best >= 3.4e38f) result = set_error(FCC_ERR_HIP, "no front-end tiling ran");
+  b->stft_tuning = best_s;
+  // the pair stage reads the spectra of the chosen front end
+  if (result == FCC_OK && time_of([&] { return fcc::launch_batch_stft(r, b->stft_tuning); }) >= 3.4e38f)
+    result = set_error(FCC_ERR_HIP, "front end failed");
+  for (size_t c = 0; c < b->classes.size() && result == FCC_OK; ++c) {
+    best = 3.4e38f;
+    fcc::PairTuning best_p = b->pair_tuning[c];
+    for (int ft : {4, 8, 16, 32, 64})
+      for (int waves : {2, 4})
+        for (int bpc : {1, 2, 3}) {
+          const fcc::PairTuning t{ft, waves, bpc};
+          const float ms = time_of([&] { return fcc::launch_batch_pair(r, b->classes[c], t); });
+          if (ms < best) {
+            best = ms;
+            best_p = t;
+          }
+        }
+    if (best >= 3.4e38f) result = set_error(FCC_ERR_HIP, "no pair tiling ran");
+    b->pair_tuning[c] = best_p;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  return result;
+}
+
+fcc_status fcc_batch_tuning(fcc_batch b, int32_t* values, int32_t capacity) {
+  if (!b || !values) return set_error(FCC_ERR_INVALID_ARG, "NULL argument");
+  const int32_t need = 2 + 3 * int32_t(b->classes.size());
+  if (capacity < need) return set_error(FCC_ERR_INVALID_ARG, "capacity below 2 + 3 * num_classes");
+  values[0] = b->stft_tuning.chunk;
+  values[1] = b->stft_tuning.blocks_per_cu;
+  for (size_t c = 0; c < b->classes.size(); ++c) {
+    values[2 + 3 * c] = b->pair_tuning[c].ft;
+    values[3 + 3 * c] = b->pair_tuning[c].waves;
+    values[4 + 3 * c] = b->pair_tuning[c].blocks_per_cu;
+  }
+  return FCC_OK;
 }
 
 const char* fcc_status_string(fcc_status status) {

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "fcc.h"
 
 namespace fcc {
@@ -19,6 +21,61 @@ struct StftArgs {
   bool raw;                  // true: X itself (FP32 only), false: X / |X|
   hipStream_t stream;
 };
+
+// ---- batches of independent arrays ------------------------------------------
+// One array of a batch as the device sees it (a table in the batch image).
+struct BatchArray {
+  int32_t M, P, N, hop, I, lag0;
+  int64_t T;                 // frames
+  int64_t L;                 // samples per microphone = row stride of its audio block
+  int64_t audio_off;         // float offset of its [M][L] audio block
+  int64_t spec_off;          // byte offset of its spectra in the workspace
+  int64_t tdoa_off;          // element offset of its [T][P] output
+  int64_t img_off;           // byte offset of its plan tables in the batch image
+  int64_t tab_twiddle, tab_pairs, tab_prow16, tab_gexp;   // table offsets inside its plan tables
+  int64_t stft_first;        // index of its first front-end item
+};
+
+// Arrays sharing one matrix-core tile shape (host side).
+struct BatchClass {
+  int index = 0;             // queue slot
+  int kb = 0, tt = 0;        // components in blocks of 4, lags in tiles of 16
+  int member_first = 0, member_count = 0;   // slice of the member list
+  std::vector<int64_t> member_frames;
+  int head_words_max = 0, slab_words_max = 0;
+  int64_t items(int ft) const;
+};
+
+struct StftTuning {
+  int chunk = 4;             // consecutive items per queue grab
+  int blocks_per_cu = 3;
+};
+struct PairTuning {
+  int ft = 16;               // frames per item
+  int waves = 4;             // wavefronts per workgroup
+  int blocks_per_cu = 2;
+};
+
+struct BatchRun {
+  const BatchArray* arrays;  // device
+  int n_arrays;
+  const int32_t* members;    // device: member lists of every class, back to back
+  const unsigned char* image;
+  const float* audio;
+  unsigned char* spec;
+  int32_t* tdoa;
+  int* queue;                // device counters: [0] front end, [1 + c] class c
+  int64_t stft_items;
+  std::vector<int> sizes;    // frame sizes present
+  fcc_precision precision;
+  hipStream_t stream;
+};
+
+hipError_t launch_batch_stft(const BatchRun& r, const StftTuning& t);
+hipError_t launch_batch_pair(const BatchRun& r, const BatchClass& c, const PairTuning& t);
+int stft_transforms_per_block(int N);
+int batch_head_words(int Dpad, int NH, int TT, int P);   // LDS words before the wavefront slabs
+int batch_slab_words(int N, int I);                      // LDS words of one wavefront slab
 
 // direction-of-arrival search over a direction grid
 struct DoaArgs {

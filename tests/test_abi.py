@@ -201,3 +201,46 @@ def test_doa_table_matches_oracle(fcc):
         bad[3, 1] = np.nan
         assert lib.fcc_doa_table(p._h, bad.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), d.shape[0],
                                  tab.ctypes.data_as(ctypes.c_void_p)) == -1
+
+
+def test_batch_validation_and_layout(fcc):
+    from gen import batch_arrays
+    arrays = batch_arrays(4000, 6, 0.3)
+    plans = [fcc.Plan(a["xyz"], a["fs"], frame_size=a["N"], hop=a["hop"], rank=0, precision="fp16")
+             for a in arrays]
+    # the rank per geometry: tau_max + 1
+    plans = [fcc.Plan(a["xyz"], a["fs"], frame_size=a["N"], hop=a["hop"], rank=p.tau_max + 1, precision="fp16")
+             for a, p in zip(arrays, plans)]
+    lengths = [a["x"].shape[1] for a in arrays]
+    lib = fcc._lib.load()
+    n = len(plans)
+    h = ctypes.c_void_p()
+    hs = (ctypes.c_void_p * n)(*[p._h for p in plans])
+    ls = (ctypes.c_int64 * n)(*lengths)
+    assert lib.fcc_batch_create(hs, n, ls, ctypes.byref(h)) == 0
+    info = fcc._lib.FccBatchInfo()
+    assert lib.fcc_batch_query(h, ctypes.byref(info)) == 0
+    ao, to, nf = (ctypes.c_int64 * n)(), (ctypes.c_int64 * n)(), (ctypes.c_int64 * n)()
+    assert lib.fcc_batch_layout(h, ao, to, nf) == 0
+    exp_a = np.cumsum([0] + [p.M * L for p, L in zip(plans, lengths)])
+    exp_f = [p.num_frames(L) for p, L in zip(plans, lengths)]
+    exp_t = np.cumsum([0] + [T * p.P for T, p in zip(exp_f, plans)])
+    assert list(ao) == list(exp_a[:-1]) and info.audio_floats == exp_a[-1]
+    assert list(nf) == exp_f and list(to) == list(exp_t[:-1]) and info.tdoa_count == exp_t[-1]
+    assert info.num_arrays == n and 1 <= info.num_classes <= n
+    assert info.image_bytes % 256 == 0 and info.workspace_bytes % 256 == 0
+    lib.fcc_batch_destroy(h)
+    # refusals
+    bad = [plans[0], fcc.Plan(arrays[1]["xyz"], arrays[1]["fs"], frame_size=512, hop=128, precision="bf16")]
+    hs = (ctypes.c_void_p * 2)(*[p._h for p in bad])
+    assert lib.fcc_batch_create(hs, 2, (ctypes.c_int64 * 2)(100, 100), ctypes.byref(h)) == -1   # mixed precision
+    for kw in [dict(precision="fp32"), dict(precision="fp16", alpha=0.5), dict(precision="fp16", method="gcc")]:
+        q = fcc.Plan(square_array(0.05), 16000.0, **kw) if kw.get("alpha", 1.0) == 1.0 or kw.get("precision") == "fp32" \
+            else None
+        if q is None:
+            continue
+        hs = (ctypes.c_void_p * 1)(q._h)
+        assert lib.fcc_batch_create(hs, 1, (ctypes.c_int64 * 1)(1000), ctypes.byref(h)) == -2, kw
+    big = fcc.Plan(circular_array(17, 0.05), 16000.0, precision="fp16")
+    hs = (ctypes.c_void_p * 1)(big._h)
+    assert lib.fcc_batch_create(hs, 1, (ctypes.c_int64 * 1)(1000), ctypes.byref(h)) == -2

@@ -1,0 +1,84 @@
+"""Batches of heterogeneous arrays on the GPU: every array's output equals the
+single-array path bit for bit (same kernels, same arithmetic), with and
+without the graph, after autotuning, and on repeated graph replays."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle.fcc_oracle as O
+from gen import batch_arrays
+from tests.parity import tdoa_report, corr_errors
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"\n[case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+@pytest.fixture(scope="module")
+def fcc():
+    import paper_2204_13622_amd as fcc
+    fcc._lib.load()
+    return fcc
+
+
+def _plans(fcc, arrays, precision):
+    out = []
+    for a in arrays:
+        p0 = fcc.Plan(a["xyz"], a["fs"], frame_size=a["N"], hop=a["hop"], precision=precision)
+        out.append(fcc.Plan(a["xyz"], a["fs"], frame_size=a["N"], hop=a["hop"], rank=p0.tau_max + 1,
+                            precision=precision))
+    return out
+
+
+@pytest.mark.parametrize("precision,count,seconds", [("fp16", 24, 0.3), ("bf16", 9, 0.2)])
+def test_batch_equals_single_arrays(torch, fcc, precision, count, seconds):
+    _say(f"batch {precision} {count} arrays")
+    arrays = batch_arrays(4100 + count, count, seconds)
+    plans = _plans(fcc, arrays, precision)
+    b = fcc.Batch(plans, [a["x"].shape[1] for a in arrays])
+    audio = b.pack([torch.from_numpy(a["x"]) for a in arrays])
+    expect = [p.tdoa(torch.from_numpy(a["x"]).cuda()).cpu().numpy() for p, a in zip(plans, arrays)]
+    for graph in (False, True):
+        got = [t.cpu().numpy().copy() for t in b.split(b.tdoa(audio, graph=graph))]
+        for a, (g, e) in enumerate(zip(got, expect)):
+            assert np.array_equal(g, e), (graph, a)
+    tuned = b.tune(audio)
+    print("tuning:", tuned, flush=True)
+    assert len(tuned["pair_classes"]) == b.info.num_classes
+    # graph replays with eager work of the same library in between
+    for rep in range(3):
+        out = b.tdoa(audio, graph=True)
+        plans[rep].tdoa(torch.from_numpy(arrays[rep]["x"]).cuda())
+        torch.cuda.synchronize()
+        for a, (g, e) in enumerate(zip(b.split(out), expect)):
+            assert np.array_equal(g.cpu().numpy(), e), (rep, a)
+
+
+def test_batch_against_oracle(torch, fcc):
+    """Two arrays of the batch through the FP64 oracle on the same quantised spectra."""
+    _say("batch vs oracle")
+    from paper_2204_13622_amd import Plan
+    arrays = batch_arrays(4200, 6, 0.25)
+    plans = _plans(fcc, arrays, "fp16")
+    b = fcc.Batch(plans, [a["x"].shape[1] for a in arrays])
+    out = b.split(b.tdoa(b.pack([torch.from_numpy(a["x"]) for a in arrays])))
+    for a in (0, 3):
+        p, x = plans[a], arrays[a]["x"]
+        spec = p.spectra(torch.from_numpy(x).cuda()).cpu().numpy().astype(np.float64)
+        e = Plan.unpack_spectrum(spec)
+        R = np.stack([e[:, i] * np.conj(e[:, j]) for i, j in O.mic_pairs(p.M)], axis=1)
+        y_ref = O.fcc_corr(R, O.fcc_basis(p.N, p.tau_max, p.rank))
+        rep = tdoa_report(out[a].cpu().numpy(), y_ref, p.tau_max, 5e-3)
+        assert rep["mismatch_qualified"] == 0 and rep["invalid_elsewhere"] == 0, rep
