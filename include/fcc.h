@@ -307,7 +307,9 @@ fcc_status fcc_batch_tuning(fcc_batch batch, int32_t* values, int32_t capacity);
 size_t fcc_mlp_num_params(int32_t in_dim, int32_t hidden);
 fcc_status fcc_mlp_workspace_bytes(int32_t in_dim, int32_t hidden, int64_t rows, size_t* bytes);
 
-/* d_coef [rows][in_dim] -> d_out [rows][2] = (mu, s). */
+/* d_coef [rows][in_dim] -> d_out [rows][2] = (mu, s).  For in_dim <= 64 and
+ * hidden 32, 64 or 128 one fused kernel keeps the hidden layers on chip (the
+ * workspace is then unused); other shapes run layer by layer. */
 fcc_status fcc_mlp_forward(const float* d_params, int32_t in_dim, int32_t hidden, const float* d_coef,
                            int64_t rows, float* d_out, void* d_workspace, hipStream_t stream);
 

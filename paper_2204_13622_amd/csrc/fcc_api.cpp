@@ -417,6 +417,8 @@ fcc_status fcc_mlp_forward(const float* d_params, int32_t in_dim, int32_t hidden
   if (st != FCC_OK) return st;
   if (rows == 0) return FCC_OK;
   if (!d_params || !d_coef || !d_out || !d_workspace) return set_error(FCC_ERR_INVALID_ARG, "NULL pointer");
+  if (fcc::mlp_fused_supported(in_dim, hidden))
+    return hip_status(fcc::mlp_infer(d_params, in_dim, hidden, d_coef, rows, d_out, stream), "fused mlp launch");
   return hip_status(fcc::mlp_forward(d_params, in_dim, hidden, d_coef, rows, d_out, d_workspace, stream),
                     "mlp forward launch");
 }
@@ -457,6 +459,7 @@ LearnedCarve learned_carve(const fcc::Plan& p, int hidden, int64_t T) {
   c.out = c.fallback + round256(sizeof(float) * size_t(R));
   c.mlp = c.out + round256(sizeof(float) * size_t(R) * 2);
   c.total = c.mlp + round256(sizeof(float) * fcc::mlp_workspace_floats(2 * p.D, hidden, R));
+  if (fcc::mlp_fused_supported(2 * p.D, hidden)) c.total = c.out;   // the fused kernel keeps the layers on chip
   return c;
 }
 }  // namespace
@@ -493,6 +496,10 @@ fcc_status fcc_tdoa_learned(fcc_plan plan, const void* d_basis, const void* d_sp
   if ((st = pair_stage(p, d_basis, d_spec, num_frames, nullptr, nullptr, stream, coef)) != FCC_OK) return st;
   if ((st = pair_stage(p, d_basis, d_spec, num_frames, nullptr, nullptr, stream, nullptr, fallback)) != FCC_OK)
     return st;
+  if (fcc::mlp_fused_supported(2 * p.D, hidden))
+    return hip_status(fcc::mlp_infer_select(d_params, 2 * p.D, hidden, coef, R, fallback, min_confidence, d_tau,
+                                            d_confidence, stream),
+                      "fused mlp launch");
   if ((st = hip_status(fcc::mlp_forward(d_params, 2 * p.D, hidden, coef, R, out, ws + c.mlp, stream),
                        "mlp forward launch")) != FCC_OK)
     return st;

@@ -141,6 +141,11 @@ hipError_t mlp_forward(const float* theta, int in_dim, int hidden, const float* 
                        void* ws, hipStream_t st);
 hipError_t mlp_backward(const float* theta, int in_dim, int hidden, const float* x, const float* delta,
                         int64_t rows, float* grad, float* loss_sum, float* out, void* ws, hipStream_t st);
+bool mlp_fused_supported(int in_dim, int hidden);
+hipError_t mlp_infer(const float* theta, int in_dim, int hidden, const float* x, int64_t rows, float* out,
+                     hipStream_t st);
+hipError_t mlp_infer_select(const float* theta, int in_dim, int hidden, const float* x, int64_t rows,
+                            const float* fallback, float min_conf, float* tau, float* conf, hipStream_t st);
 hipError_t mlp_select(const float* out, const float* fallback, int64_t rows, float min_conf, float* tau,
                       float* conf, hipStream_t st);
 hipError_t mlp_adam(float* theta, float* m, float* v, const float* grad, int64_t n, float lr, float b1, float b2,

@@ -206,7 +206,7 @@ struct Layout {
   int K0, H;
   size_t W1, b1, W2, b2, W3, b3, total;
 };
-Layout layout(int K0, int H) {
+__host__ __device__ Layout layout(int K0, int H) {
   Layout L{K0, H, 0, 0, 0, 0, 0, 0, 0};
   size_t o = 0;
   L.W1 = o; o += size_t(K0) * H;
@@ -259,7 +259,219 @@ hipError_t forward_impl(const float* theta, int K0, int H, const float* x, int64
   return hipGetLastError();
 }
 
+// ---- fused inference ---------------------------------------------------------
+// Every wavefront takes 16 rows at a time through all three layers: the
+// normalised coefficients go straight into the A-operand registers of the
+// 16x16x32 FP16 MFMA, the layer outputs pass through a per-wavefront FP16
+// row buffer in LDS (the C layout of one layer is not the A layout of the
+// next), and the two head outputs are dot products on the vector ALU.  The
+// weights sit in LDS, transposed ([n][k]) as the B operands want them.  The
+// rounding points are those of the layer-by-layer path: operands of every
+// product in FP16, accumulation, bias, GELU and head in FP32.
+
+__device__ __forceinline__ float gelu_fast(float x) {
+  // tanh(u) = 1 - 2 / (1 + exp(2u)): exact at both tails (exp over- and underflow)
+  const float u = kGeluC * (x + kGeluA * x * x * x);
+  const float t = 1.f - 2.f / (1.f + __expf(2.f * u));
+  return 0.5f * x * (1.f + t);
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int K0P, int H>
+struct InferLds {
+  static constexpr int W1ROW = K0P + 8, W2ROW = H + 8, HROW = H + 8;   // halves; pads spread the banks
+  static constexpr size_t bytes(int waves) {
+    return sizeof(_Float16) * (size_t(H) * W1ROW + size_t(H) * W2ROW + size_t(waves) * 16 * HROW) +
+           sizeof(float) * (3 * size_t(H) + 2 * size_t(H) + 4);
+  }
+};
+
+// out: (mu, s) per row, or with `fallback` the learned lag where exp(-s/2) >=
+// min_conf and the fallback elsewhere into tau, with exp(-s/2) into conf
+template <int K0P, int H>
+__global__ __launch_bounds__(256) void mlp_infer_kernel(const float* __restrict__ theta, int K0,
+                                                        const float* __restrict__ x, int64_t R,
+                                                        float* __restrict__ out, const float* __restrict__ fallback,
+                                                        float min_conf, float* __restrict__ tau,
+                                                        float* __restrict__ conf) {
+  using LY = InferLds<K0P, H>;
+  constexpr int kWaves = 4;
+  extern __shared__ __attribute__((aligned(16))) unsigned char lds_raw[];
+  _Float16* w1t = reinterpret_cast<_Float16*>(lds_raw);                  // [H][W1ROW]
+  _Float16* w2t = w1t + H * LY::W1ROW;                                    // [H][W2ROW]
+  _Float16* hb_all = w2t + H * LY::W2ROW;                                 // [waves][16][HROW]
+  float* b1 = reinterpret_cast<float*>(hb_all + kWaves * 16 * LY::HROW);  // [H]
+  float* b2 = b1 + H;                                                     // [H]
+  float* w3 = b2 + H;                                                     // [H][2], FP16-rounded
+  float* b3 = w3 + 2 * H;                                                 // [2]
+  const Layout L = layout(K0, H);
+  for (int e = threadIdx.x; e < H * K0P; e += 256) {
+    const int n = e / K0P, k = e % K0P;
+    w1t[n * LY::W1ROW + k] = (_Float16)(k < K0 ? theta[L.W1 + (size_t)k * H + n] : 0.f);
+  }
+  for (int e = threadIdx.x; e < H * H; e += 256) {
+    const int n = e / H, k = e % H;
+    w2t[n * LY::W2ROW + k] = (_Float16)theta[L.W2 + (size_t)k * H + n];
+  }
+  for (int e = threadIdx.x; e < H; e += 256) {
+    b1[e] = theta[L.b1 + e];
+    b2[e] = theta[L.b2 + e];
+    w3[2 * e] = (float)(_Float16)theta[L.W3 + 2 * e];
+    w3[2 * e + 1] = (float)(_Float16)theta[L.W3 + 2 * e + 1];
+  }
+  if (threadIdx.x < 2) b3[threadIdx.x] = theta[L.b3 + threadIdx.x];
+  __syncthreads();
+
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int g = lane >> 4, col = lane & 15;
+  _Float16* hb = hb_all + wave * 16 * LY::HROW;
+  const int64_t groups = (R + 15) / 16;
+  for (int64_t grp = (int64_t)blockIdx.x * kWaves + wave; grp < groups; grp += (int64_t)gridDim.x * kWaves) {
+    const int64_t row = grp * 16 + col;                   // this lane's row as an A operand
+    // features: u = c / ||c||, straight into the A layout (k = 8 g + 32 kk + i)
+    float v[K0P / 32][8];
+    float n2 = 0.f;
+#pragma unroll
+    for (int kk = 0; kk < K0P / 32; ++kk)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int k = 32 * kk + 8 * g + i;
+        const float c = (row < R && k < K0) ? x[row * K0 + k] : 0.f;
+        v[kk][i] = c;
+        n2 += c * c;
+      }
+    n2 += __shfl_xor(n2, 16);
+    n2 += __shfl_xor(n2, 32);
+    const float sc = n2 > 0.f ? rsqrtf(n2) : 0.f;
+    h8 a1[K0P / 32];
+#pragma unroll
+    for (int kk = 0; kk < K0P / 32; ++kk)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) a1[kk][i] = (_Float16)(v[kk][i] * sc);
+
+    // layer 1 -> hb
+#pragma unroll
+    for (int nt = 0; nt < H / 16; ++nt) {
+      f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kk = 0; kk < K0P / 32; ++kk) {
+        const h8 bw = *reinterpret_cast<const h8*>(w1t + (16 * nt + col) * LY::W1ROW + 32 * kk + 8 * g);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(a1[kk], bw, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int n = 16 * nt + col;
+        hb[(4 * g + q) * LY::HROW + n] = (_Float16)gelu_fast(acc[q] + b1[n]);
+      }
+    }
+    wave_sync();
+    h8 a2[H / 32];
+#pragma unroll
+    for (int kk = 0; kk < H / 32; ++kk) a2[kk] = *reinterpret_cast<const h8*>(hb + col * LY::HROW + 32 * kk + 8 * g);
+    wave_sync();                                          // every lane holds its operands: hb takes layer 2
+    // layer 2 -> hb
+#pragma unroll
+    for (int nt = 0; nt < H / 16; ++nt) {
+      f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kk = 0; kk < H / 32; ++kk) {
+        const h8 bw = *reinterpret_cast<const h8*>(w2t + (16 * nt + col) * LY::W2ROW + 32 * kk + 8 * g);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(a2[kk], bw, acc, 0, 0, 0);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int n = 16 * nt + col;
+        hb[(4 * g + q) * LY::HROW + n] = (_Float16)gelu_fast(acc[q] + b2[n]);
+      }
+    }
+    wave_sync();
+    // layer 3 and head: lane (row col, quarter g) sums a quarter of the hidden units
+    float s0 = 0.f, s1 = 0.f;
+#pragma unroll 8
+    for (int k = g * (H / 4); k < (g + 1) * (H / 4); ++k) {
+      const float h = (float)hb[col * LY::HROW + k];
+      s0 += h * w3[2 * k];
+      s1 += h * w3[2 * k + 1];
+    }
+    s0 += __shfl_xor(s0, 16);
+    s1 += __shfl_xor(s1, 16);
+    s0 += __shfl_xor(s0, 32);
+    s1 += __shfl_xor(s1, 32);
+    if (g == 0 && row < R) {
+      const float mu = s0 + b3[0];
+      const float s = fminf(fmaxf(s1 + b3[1], -kSClip), kSClip);
+      if (fallback) {
+        const float c = expf(-0.5f * s);
+        tau[row] = c >= min_conf ? mu : fallback[row];
+        if (conf) conf[row] = c;
+      } else {
+        out[2 * row] = mu;
+        out[2 * row + 1] = s;
+      }
+    }
+    wave_sync();                                          // hb is rewritten by the next group
+  }
+}
+
+template <int K0P, int H>
+hipError_t launch_infer(const float* theta, int K0, const float* x, int64_t R, float* out, const float* fallback,
+                        float min_conf, float* tau, float* conf, hipStream_t st) {
+  const size_t lds = InferLds<K0P, H>::bytes(4);
+  auto k = mlp_infer_kernel<K0P, H>;
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
+  }
+  const int64_t groups = (R + 15) / 16;
+  int64_t blocks = (groups + 3) / 4;
+  if (blocks > 2 * (int64_t)cus) blocks = 2 * (int64_t)cus;    // persistent: two workgroups per CU
+  hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(256), lds, st, theta, K0, x, R, out, fallback, min_conf, tau, conf);
+  return hipGetLastError();
+}
+
+// the fused kernel's shapes: in_dim <= 64, hidden 32, 64 or 128
+hipError_t infer_dispatch(const float* theta, int K0, int H, const float* x, int64_t R, float* out,
+                          const float* fallback, float min_conf, float* tau, float* conf, hipStream_t st) {
+  if (K0 <= 32) {
+    if (H == 32) return launch_infer<32, 32>(theta, K0, x, R, out, fallback, min_conf, tau, conf, st);
+    if (H == 64) return launch_infer<32, 64>(theta, K0, x, R, out, fallback, min_conf, tau, conf, st);
+    if (H == 128) return launch_infer<32, 128>(theta, K0, x, R, out, fallback, min_conf, tau, conf, st);
+  } else if (K0 <= 64) {
+    if (H == 32) return launch_infer<64, 32>(theta, K0, x, R, out, fallback, min_conf, tau, conf, st);
+    if (H == 64) return launch_infer<64, 64>(theta, K0, x, R, out, fallback, min_conf, tau, conf, st);
+    if (H == 128) return launch_infer<64, 128>(theta, K0, x, R, out, fallback, min_conf, tau, conf, st);
+  }
+  return hipErrorNotSupported;
+}
+
 }  // namespace
+
+bool mlp_fused_supported(int in_dim, int hidden) {
+  return in_dim >= 1 && in_dim <= 64 && (hidden == 32 || hidden == 64 || hidden == 128);
+}
+
+hipError_t mlp_infer(const float* theta, int in_dim, int hidden, const float* x, int64_t rows, float* out,
+                     hipStream_t st) {
+  if (rows == 0) return hipSuccess;
+  return infer_dispatch(theta, in_dim, hidden, x, rows, out, nullptr, 0.f, nullptr, nullptr, st);
+}
+
+hipError_t mlp_infer_select(const float* theta, int in_dim, int hidden, const float* x, int64_t rows,
+                            const float* fallback, float min_conf, float* tau, float* conf, hipStream_t st) {
+  if (rows == 0) return hipSuccess;
+  return infer_dispatch(theta, in_dim, hidden, x, rows, nullptr, fallback, min_conf, tau, conf, st);
+}
 
 size_t mlp_num_params(int in_dim, int hidden) { return layout(in_dim, hidden).total; }
 
