@@ -97,25 +97,35 @@ __device__ __forceinline__ void transforms(const float2* tw, const float2* tw1, 
 
   if (!active) return;
   // Real split: E = (Z(f) + Z*(NH - f)) / 2, O = (Z(f) - Z*(NH - f)) / 2j,
-  // X(f) = E + W^f O and X(NH - f) = conj(E - W^f O).
+  // X(f) = E + W^f O and X(NH - f) = conj(E - W^f O).  PHAT is blind to a
+  // common factor, so the halves are dropped unless the raw X is wanted.
+  // Lane lf takes f = lf, lf + LF, ... < NH / 2 (the same number of bins on
+  // every lane); f = 0 is the DC / Nyquist slot, and its lane also takes the
+  // centre bin NH / 2, which is its own mirror.
+  constexpr float h = RAW ? 0.5f : 1.f;
   typename S::T* dst = out + b * NH;
-  for (int f = lf; f <= NH / 2; f += LF) {
+  for (int f = lf; f < NH / 2; f += LF) {
     if (f == 0) {
       // X(0) = Re Z(0) + Im Z(0), X(N/2) = Re Z(0) - Im Z(0); both real
       const float2 z0 = buf[0];
       if (RAW) dst[0] = spec_encode<S>(make_float2(z0.x + z0.y, z0.x - z0.y));
       else dst[0] = spec_encode<S>(make_float2(phat_real(z0.x + z0.y), phat_real(z0.x - z0.y)));
+      // centre: E = Re Z(NH/2), O = Im Z(NH/2), X = E + W^(NH/2) O
+      const float2 zc = buf[pidx(NH / 2)];
+      const float2 wc = tw[NH / 2];
+      const float2 Xc = make_float2(zc.x + wc.x * zc.y, wc.y * zc.y);
+      dst[NH / 2] = spec_encode<S>(RAW ? Xc : phat_complex(Xc));
       continue;
     }
     const float2 zf = buf[pidx(f)];
     const float2 zr = buf[pidx(NH - f)];
-    const float2 e = make_float2(0.5f * (zf.x + zr.x), 0.5f * (zf.y - zr.y));
-    const float2 o = make_float2(0.5f * (zf.y + zr.y), -0.5f * (zf.x - zr.x));
+    const float2 e = make_float2(h * (zf.x + zr.x), h * (zf.y - zr.y));
+    const float2 o = make_float2(h * (zf.y + zr.y), -h * (zf.x - zr.x));
     const float2 wo = cmul(tw[f], o);
     const float2 Xa = cadd(e, wo);
     const float2 Xb = make_float2(e.x - wo.x, wo.y - e.y);
     dst[f] = spec_encode<S>(RAW ? Xa : phat_complex(Xa));
-    if (f != NH - f) dst[NH - f] = spec_encode<S>(RAW ? Xb : phat_complex(Xb));
+    dst[NH - f] = spec_encode<S>(RAW ? Xb : phat_complex(Xb));
   }
 }
 
