@@ -144,7 +144,6 @@ __device__ __forceinline__ void run_frames(const uint32_t* lds_all, uint32_t* sl
   if (t < T) prefetch(t);
 
   const h8 sgn = {-1, 1, -1, 1, -1, 1, -1, 1};
-  const int micA = col & 3;
   const int nsteps = NH / 16;
 
   for (; t < T; t += stride) {
@@ -185,12 +184,13 @@ __device__ __forceinline__ void run_frames(const uint32_t* lds_all, uint32_t* sl
       for (int ib = 0; ib < 4; ++ib) acc[kb][ib] = f4{0.f, 0.f, 0.f, 0.f};
 
     const uint32_t* own = slab + col * row + 4 * g;
-    const uint32_t* amic = slab + micA * row + 4 * g;
+    const uint32_t* amic = slab + (col & 3) * row + 4 * g;
     const uint32_t* prow = ptab + (col >> 2) * prow_words + 4 * g;
     // one K step: 16 slots (32 interleaved re / im values); every tile of
     // four microphone blocks runs (rows of absent microphones are zero)
     auto kstep = [&](int off, bool dc_slot) {
-      const h8 raw = __builtin_bit_cast(h8, *reinterpret_cast<const uint4*>(own + off));
+      const uint4 rw = *reinterpret_cast<const uint4*>(own + off);
+      const h8 raw = __builtin_bit_cast(h8, rw);
       // B: the rotated spectrum (a - b, a + b) of microphone `col`; the packed
       // DC / Nyquist slot holds two real bins and enters unrotated.
       const h8 sw = __builtin_shufflevector(raw, raw, 1, 0, 3, 2, 5, 4, 7, 6);
@@ -250,18 +250,28 @@ __device__ __forceinline__ void run_frames(const uint32_t* lds_all, uint32_t* sl
       const int64_t orow = t * P + p;
       const float* ya = ybuf + i * kYRow + j;
       const float* yb = ybuf + (I - 1) * kYStride + j * kYRow + i;
-      float best = ya[0] + yb[0];
+      // all lag reads issue together (compile-time bound, guarded), then the
+      // first-index argmax
+      float y[16 * TT];
+#pragma unroll
+      for (int tau = 0; tau < 16 * TT; ++tau)
+        y[tau] = tau < I ? ya[tau * kYStride] + yb[-tau * kYStride] : 0.f;
+      float best = y[0];
       int bi = 0;
-      if (WRITE_Y) yout[orow * I] = best;
-      for (int tau = 1; tau < I; ++tau) {
-        const float v = ya[tau * kYStride] + yb[-tau * kYStride];
-        if (WRITE_Y) yout[orow * I + tau] = v;
-        if (v > best) {
-          best = v;
+#pragma unroll
+      for (int tau = 1; tau < 16 * TT; ++tau) {
+        if (tau < I && y[tau] > best) {
+          best = y[tau];
           bi = tau;
         }
       }
-      if (!WRITE_Y) tdoa[orow] = bi - lag0;
+      if (WRITE_Y) {
+#pragma unroll
+        for (int tau = 0; tau < 16 * TT; ++tau)
+          if (tau < I) yout[orow * I + tau] = y[tau];
+      } else {
+        tdoa[orow] = bi - lag0;
+      }
     }
     wave_sync();   // the slab is rewritten by the next frame
   }
