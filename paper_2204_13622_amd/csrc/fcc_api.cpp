@@ -493,8 +493,8 @@ fcc_status fcc_tdoa_learned(fcc_plan plan, const void* d_basis, const void* d_sp
   float* coef = reinterpret_cast<float*>(ws + c.coef);
   float* fallback = reinterpret_cast<float*>(ws + c.fallback);
   float* out = reinterpret_cast<float*>(ws + c.out);
-  if ((st = pair_stage(p, d_basis, d_spec, num_frames, nullptr, nullptr, stream, coef)) != FCC_OK) return st;
-  if ((st = pair_stage(p, d_basis, d_spec, num_frames, nullptr, nullptr, stream, nullptr, fallback)) != FCC_OK)
+  // one pass over the spectra gives both the coefficients and the interpolated lag
+  if ((st = pair_stage(p, d_basis, d_spec, num_frames, nullptr, nullptr, stream, coef, fallback)) != FCC_OK)
     return st;
   if (fcc::mlp_fused_supported(2 * p.D, hidden))
     return hip_status(fcc::mlp_infer_select(d_params, 2 * p.D, hidden, coef, R, fallback, min_confidence, d_tau,

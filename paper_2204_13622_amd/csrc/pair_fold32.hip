@@ -11,7 +11,8 @@
 // and accumulates z_k += p_hat_k(f) x_s (symmetric k) or p_hat_k(f) x_d
 // (antisymmetric k).  The second group leaves its partial coefficients in
 // LDS; the first adds them and the centre bin.  Outputs, by mode: the
-// coefficients (a_k, b_k) themselves; or the expansion to the I lags through
+// coefficients (a_k, b_k) themselves (optionally together with the
+// interpolated lag, in one pass); or the expansion to the I lags through
 // the dictionary (2 Dc, -2 Ds) followed by the first-index argmax, written as
 // the integer lag, as the lag refined by quadratic interpolation around the
 // maximum (Sec. 2), or as the correlation y itself.
@@ -25,14 +26,14 @@ namespace fcc {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kOutLag = 0, kOutCorr = 1, kOutCoef = 2, kOutParabolic = 3;
+constexpr int kOutLag = 0, kOutCorr = 1, kOutCoef = 2, kOutParabolic = 3, kOutCoefParabolic = 4;
 
 template <class S, int DB, int OUT>
 __global__ __launch_bounds__(kThreads) void pair_fold32_kernel(
     const typename S::T* __restrict__ spec, int M, int P, int N, int I, int lag0, float inv_r,
     const uint8_t* __restrict__ pairs, const float* __restrict__ pfold /*[N/4+1][DB]*/,
     const float* __restrict__ dict /*[I][2D]*/, int D, int32_t* __restrict__ tdoa,
-    float* __restrict__ fout) {
+    float* __restrict__ fout, float* __restrict__ fcoef) {
   extern __shared__ float smem[];
   const int NH = N / 2, F = NH + 1, m = N / 4;
   float2* sp = reinterpret_cast<float2*>(smem);          // [M][F]
@@ -103,12 +104,13 @@ __global__ __launch_bounds__(kThreads) void pair_fold32_kernel(
         }
       }
       const int64_t row = t * P + p;
-      if (OUT == kOutCoef) {
+      if (OUT == kOutCoef || OUT == kOutCoefParabolic) {
         for (int k = 0; k < D && k < DB; ++k) {
-          fout[row * 2 * D + 2 * k] = a[k];
-          fout[row * 2 * D + 2 * k + 1] = b[k];
+          fcoef[row * 2 * D + 2 * k] = a[k];
+          fcoef[row * 2 * D + 2 * k + 1] = b[k];
         }
-      } else {
+      }
+      if (OUT != kOutCoef) {
         float best = 0.f, prev = 0.f, y_lo = 0.f, y_hi = 0.f;
         int bi = 0;
         for (int ii = 0; ii < I; ++ii) {
@@ -127,7 +129,7 @@ __global__ __launch_bounds__(kThreads) void pair_fold32_kernel(
           prev = y;
         }
         if (OUT == kOutLag) tdoa[row] = bi - lag0;                  // units of 1/r sample
-        if (OUT == kOutParabolic) {
+        if (OUT == kOutParabolic || OUT == kOutCoefParabolic) {
           // vertex of the parabola through (-1, y_lo), (0, best), (1, y_hi);
           // no refinement at the window edges or on a flat top
           float d = 0.f;
@@ -156,15 +158,16 @@ hipError_t launch3(const PairArgs& a) {
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  float* fout = OUT == kOutCorr ? a.y : (OUT == kOutCoef ? a.coef : a.tau_frac);
+  float* fout = OUT == kOutCorr ? a.y : a.tau_frac;
   hipLaunchKernelGGL(k, dim3((unsigned)a.T), dim3(kThreads), lds, a.stream,
                      static_cast<const typename S::T*>(a.spec), a.M, a.P, a.N, a.I, a.lag0, 1.f / (float)a.r,
-                     a.pairs, a.pfold, a.dict, a.D, a.tdoa, fout);
+                     a.pairs, a.pfold, a.dict, a.D, a.tdoa, fout, a.coef);
   return hipGetLastError();
 }
 
 template <class S, int DB>
 hipError_t launch2(const PairArgs& a) {
+  if (a.coef && a.tau_frac) return launch3<S, DB, kOutCoefParabolic>(a);
   if (a.coef) return launch3<S, DB, kOutCoef>(a);
   if (a.tau_frac) return launch3<S, DB, kOutParabolic>(a);
   if (a.y) return launch3<S, DB, kOutCorr>(a);
