@@ -49,17 +49,68 @@ Chunking chunking(int64_t T, int P) {
   return c;
 }
 
-// raw spectrum of one microphone in the packed layout: slot 0 = (X(0), X(N/2))
-__device__ __forceinline__ void load_bins(const float2* __restrict__ x, int f, int NH, float2& lo, float2& hi) {
-  if (f == 0) {
-    const float2 v = x[0];
-    lo = make_float2(v.x, 0.f);
-    hi = make_float2(v.y, 0.f);
-  } else {
-    lo = x[f];
-    hi = x[NH - f];
+// Every supported N >= 128 gives N/4 = 16 S folded bins, so each lane of a
+// pair owns exactly S of them; only N <= 64 (S = 1) leaves lanes idle.
+template <int S>
+__device__ __forceinline__ bool owns_bin(int f, int m) { return S > 1 || f < m; }
+
+// Where a lane reads its bins: bin f = lane + 16 s of a microphone sits at
+// lo + 16 s and bin N/2 - f at hi - 16 s (for s >= 1; slot 0 of lane 0 is the
+// packed (X(0), X(N/2)) pair of the spectrum layout).  The pointers step one
+// frame at a time, so every load is a base plus a constant offset.
+struct BinPtrs {
+  const float2* lo;
+  const float2* hi;
+  __device__ __forceinline__ BinPtrs(const float2* row, int NH, int lane) : lo(row + lane), hi(row + NH - lane) {}
+  __device__ __forceinline__ void advance(int64_t stride) {
+    lo += stride;
+    hi += stride;
   }
-}
+};
+
+// Slot group of one frame, branch-free: bins f and N/2 - f of microphones i
+// and j for slots s0 .. s0 + G - 1 of a lane.  Large N loads and consumes a
+// frame in groups of at most 8 slots so that the loads in flight stay within
+// the register file.
+constexpr int kSlotGroup = 8;
+
+template <int S, int G>
+struct SlotBins {
+  float2 il[G], ih[G], jl[G], jh[G];
+  __device__ __forceinline__ void load(const BinPtrs& pi, const BinPtrs& pj, int m, int lane, int s0) {
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      const int s = s0 + g;
+      il[g] = ih[g] = jl[g] = jh[g] = make_float2(0.f, 0.f);
+      if (owns_bin<S>(lane + 16 * s, m)) {
+        il[g] = pi.lo[16 * s];
+        jl[g] = pj.lo[16 * s];
+        if (s > 0) {
+          ih[g] = pi.hi[-16 * s];
+          jh[g] = pj.hi[-16 * s];
+        } else {
+          // slot 0: bin N/2 - lane for lanes 1..15; lane 0 unpacks DC and Nyquist
+          const bool dc = lane == 0;
+          ih[g] = (dc ? pi.lo : pi.hi)[0];
+          jh[g] = (dc ? pj.lo : pj.hi)[0];
+          ih[g] = dc ? make_float2(il[g].y, 0.f) : ih[g];
+          jh[g] = dc ? make_float2(jl[g].y, 0.f) : jh[g];
+          il[g].y = dc ? 0.f : il[g].y;
+          jl[g].y = dc ? 0.f : jl[g].y;
+        }
+      }
+    }
+  }
+};
+
+// the centre bin N/4: every lane reads it, lane 0 alone owns it
+struct CentreBin {
+  float2 ci, cj;
+  __device__ __forceinline__ void load(const BinPtrs& pi, const BinPtrs& pj, int m, int lane) {
+    ci = (pi.lo - lane)[m];
+    cj = (pj.lo - lane)[m];
+  }
+};
 
 __device__ __forceinline__ float2 smooth_step(float2 R, float2 a, float2 b, float alpha, float beta) {
   const float2 c = cmul_conj(a, b);
@@ -68,9 +119,61 @@ __device__ __forceinline__ float2 smooth_step(float2 R, float2 a, float2 b, floa
 
 __device__ __forceinline__ float2 phat_pair(float2 R) {
   const float n2 = R.x * R.x + R.y * R.y;
-  if (n2 < 1.17549435e-38f) return make_float2(0.f, 0.f);
-  const float s = rsqrtf(n2);
+  const float s = n2 < 1.17549435e-38f ? 0.f : rsqrtf(n2);   // a vanishing bin contributes nothing
   return make_float2(R.x * s, R.y * s);
+}
+
+// Cross-lane exchange inside a row of 16 lanes (the pair's lanes) through DPP
+// row permutations: the mirrored lane 15 - l, the mirror inside each half
+// row, and the lanes at xor 1 and xor 2 inside each quad.  Applied in that
+// order the four steps pair every lane with a disjoint set each time, so a
+// reduction leaves the full result, bit-identical, on all 16 lanes.
+constexpr int kDppRowMirror = 0x140, kDppRowHalfMirror = 0x141, kDppQuadXor1 = 0xB1, kDppQuadXor2 = 0x4E;
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __int_as_float(dpp_i<CTRL>(__float_as_int(v)));
+}
+
+__device__ __forceinline__ float row_sum16(float v) {
+  v += dpp_f<kDppRowMirror>(v);
+  v += dpp_f<kDppRowHalfMirror>(v);
+  v += dpp_f<kDppQuadXor1>(v);
+  v += dpp_f<kDppQuadXor2>(v);
+  return v;
+}
+
+// (value, index) maximum, ties to the lower index
+template <int CTRL>
+__device__ __forceinline__ void argmax_step(float& best, int& bi) {
+  const float ov = dpp_f<CTRL>(best);
+  const int oi = dpp_i<CTRL>(bi);
+  if (ov > best || (ov == best && oi < bi)) {
+    best = ov;
+    bi = oi;
+  }
+}
+
+__device__ __forceinline__ void row_argmax16(float& best, int& bi) {
+  argmax_step<kDppRowMirror>(best, bi);
+  argmax_step<kDppRowHalfMirror>(best, bi);
+  argmax_step<kDppQuadXor1>(best, bi);
+  argmax_step<kDppQuadXor2>(best, bi);
+}
+
+// Workgroups are dealt to the 8 XCDs round-robin.  Renumber them so that
+// each XCD owns a contiguous run of (chunk, pair group) indices, i.e. whole
+// chunks: every spectrum of a chunk is then read by up to M - 1 pairs through
+// one L2 instead of being fetched into several.
+__device__ __forceinline__ int64_t xcd_linear_block() {
+  constexpr unsigned kXcds = 8;
+  const unsigned nb = gridDim.x, xcd = blockIdx.x % kXcds, local = blockIdx.x / kXcds;
+  const unsigned per = nb / kXcds, extra = nb % kXcds;
+  return (int64_t)xcd * per + (xcd < extra ? xcd : extra) + local;
 }
 
 // state index of bin b of pair p
@@ -83,8 +186,9 @@ __global__ __launch_bounds__(kThreads) void smooth_local_kernel(
     const uint8_t* __restrict__ pairs, float alpha, float2* __restrict__ scratch) {
   const int NH = N / 2, m = N / 4, F = NH + 1;
   const int lane = threadIdx.x % kGroup, grp = threadIdx.x / kGroup;
-  const int pg = blockIdx.x % groups;
-  const int64_t c = blockIdx.x / groups;
+  const int64_t v = xcd_linear_block();
+  const int pg = (int)(v % groups);
+  const int64_t c = v / groups;
   const int p = pg * kPairsPerBlock + grp;
   if (p >= P) return;                       // no cross-lane work in this pass
   const int i = pairs[2 * p], j = pairs[2 * p + 1];
@@ -93,27 +197,55 @@ __global__ __launch_bounds__(kThreads) void smooth_local_kernel(
 #pragma unroll
   for (int s = 0; s < S; ++s) lo[s] = hi[s] = make_float2(0.f, 0.f);
   const int64_t t0 = c * clen, t1 = t0 + clen < T ? t0 + clen : T;
-  for (int64_t t = t0; t < t1; ++t) {
-    const float2* xi = spec + (t * M + i) * NH;
-    const float2* xj = spec + (t * M + j) * NH;
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-      const int f = lane + kGroup * s;
-      if (f < m) {
-        float2 il, ih, jl, jh;
-        load_bins(xi, f, NH, il, ih);
-        load_bins(xj, f, NH, jl, jh);
-        lo[s] = smooth_step(lo[s], il, jl, alpha, beta);
-        hi[s] = smooth_step(hi[s], ih, jh, alpha, beta);
-      }
+  const int64_t stride = (int64_t)M * NH;
+  BinPtrs pi(spec + (t0 * M + i) * NH, NH, lane), pj(spec + (t0 * M + j) * NH, NH, lane);
+  if constexpr (S <= kSlotGroup) {
+    // whole frames fit: keep the next frame's loads in flight during this one
+    SlotBins<S, S> nxt, cur;
+    CentreBin cn, cc;
+    if (t0 < t1) {
+      nxt.load(pi, pj, m, lane, 0);
+      cn.load(pi, pj, m, lane);
     }
-    if (lane == 0) ce = smooth_step(ce, xi[m], xj[m], alpha, beta);
+    for (int64_t t = t0; t < t1; ++t) {
+      cur = nxt;
+      cc = cn;
+      if (t + 1 < t1) {
+        pi.advance(stride);
+        pj.advance(stride);
+        nxt.load(pi, pj, m, lane, 0);
+        cn.load(pi, pj, m, lane);
+      }
+#pragma unroll
+      for (int s = 0; s < S; ++s) {
+        lo[s] = smooth_step(lo[s], cur.il[s], cur.jl[s], alpha, beta);
+        hi[s] = smooth_step(hi[s], cur.ih[s], cur.jh[s], alpha, beta);
+      }
+      ce = smooth_step(ce, cc.ci, cc.cj, alpha, beta);
+    }
+  } else {
+    for (int64_t t = t0; t < t1; ++t, pi.advance(stride), pj.advance(stride)) {
+#pragma unroll
+      for (int s0 = 0; s0 < S; s0 += kSlotGroup) {
+        SlotBins<S, kSlotGroup> cur;
+        cur.load(pi, pj, m, lane, s0);
+#pragma unroll
+        for (int g = 0; g < kSlotGroup; ++g) {
+          lo[s0 + g] = smooth_step(lo[s0 + g], cur.il[g], cur.jl[g], alpha, beta);
+          hi[s0 + g] = smooth_step(hi[s0 + g], cur.ih[g], cur.jh[g], alpha, beta);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      CentreBin cc;
+      cc.load(pi, pj, m, lane);
+      ce = smooth_step(ce, cc.ci, cc.cj, alpha, beta);
+    }
   }
   float2* out = scratch + c * (int64_t)P * F;
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     const int f = lane + kGroup * s;
-    if (f < m) {
+    if (owns_bin<S>(f, m)) {
       out[sidx(p, f, F)] = lo[s];
       out[sidx(p, NH - f, F)] = hi[s];
     }
@@ -138,7 +270,7 @@ __global__ void smooth_carry_kernel(const float2* __restrict__ state, float2* __
 
 // ---- pass 3: rerun each chunk from its carry and evaluate FCC --------------
 template <int S, int DB>
-__global__ __launch_bounds__(kThreads) void smooth_fcc_kernel(
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(S <= 8 && DB <= 12 ? 2 : 1))) void smooth_fcc_kernel(
     const float2* __restrict__ spec, int64_t T, int M, int P, int N, int I, int D, int lag0, float inv_r,
     int64_t clen, int groups, const uint8_t* __restrict__ pairs, float alpha,
     const float* __restrict__ pfold /*[N/4 + 1][DB]*/, const float* __restrict__ dict /*[I][2D]*/,
@@ -147,15 +279,20 @@ __global__ __launch_bounds__(kThreads) void smooth_fcc_kernel(
   extern __shared__ float lds[];
   const int NH = N / 2, m = N / 4, F = NH + 1;
   constexpr int PW = DB + 1;                      // padded basis row: conflict-free across lanes
+  constexpr int DW = 2 * PW;                      // dictionary row: 2 DB coefficients, zero past 2 D, padded
   float* pf = lds;                                // [m + 1][PW]
-  float* dc = lds + (m + 1) * PW;                 // [I][2D]
+  float* dc = lds + (m + 1) * PW;                 // [I][DW]
   for (int e = threadIdx.x; e < (m + 1) * DB; e += kThreads) pf[(e / DB) * PW + e % DB] = pfold[e];
-  for (int e = threadIdx.x; e < I * 2 * D; e += kThreads) dc[e] = dict[e];
+  for (int e = threadIdx.x; e < I * DW; e += kThreads) {
+    const int row = e / DW, col = e % DW;
+    dc[e] = col < 2 * D ? dict[row * 2 * D + col] : 0.f;
+  }
   __syncthreads();
 
   const int lane = threadIdx.x % kGroup, grp = threadIdx.x / kGroup;
-  const int pg = blockIdx.x % groups;
-  const int64_t c = blockIdx.x / groups;
+  const int64_t v = xcd_linear_block();
+  const int pg = (int)(v % groups);
+  const int64_t c = v / groups;
   const int pq = pg * kPairsPerBlock + grp;
   const bool active = pq < P;                     // idle groups mirror pair 0 so every shuffle is uniform
   const int p = active ? pq : 0;
@@ -175,74 +312,79 @@ __global__ __launch_bounds__(kThreads) void smooth_fcc_kernel(
   if (lane == 0) ce = in[sidx(p, m, F)];
 
   const int64_t t0 = c * clen, t1 = t0 + clen < T ? t0 + clen : T;
-  for (int64_t t = t0; t < t1; ++t) {
-    const float2* xi = spec + (t * M + i) * NH;
-    const float2* xj = spec + (t * M + j) * NH;
+  const int nq = (I + kGroup - 1) / kGroup;      // lag slots in use, uniform
+  const int64_t stride = (int64_t)M * NH;
+  BinPtrs pi(spec + (t0 * M + i) * NH, NH, lane), pj(spec + (t0 * M + j) * NH, NH, lane);
+  constexpr int kGroupMax = DB <= 12 ? kSlotGroup : kSlotGroup / 2;   // wide bases hold more weights per slot
+  constexpr int G = S < kGroupMax ? S : kGroupMax;
+  for (int64_t t = t0; t < t1; ++t, pi.advance(stride), pj.advance(stride)) {
+    CentreBin cc;
+    cc.load(pi, pj, m, lane);
     float a[DB], b[DB];
 #pragma unroll
     for (int k = 0; k < DB; ++k) a[k] = b[k] = 0.f;
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-      const int f = lane + kGroup * s;
-      if (f < m) {
-        float2 il, ih, jl, jh;
-        load_bins(xi, f, NH, il, ih);
-        load_bins(xj, f, NH, jl, jh);
-        lo[s] = smooth_step(lo[s], il, jl, alpha, beta);
-        hi[s] = smooth_step(hi[s], ih, jh, alpha, beta);
-        const float2 el = phat_pair(lo[s]), eh = phat_pair(hi[s]);
-        const float2 xs = cadd(el, eh), xd = csub(el, eh);            // eq. (8)
-        const float* w = pf + f * PW;
+    for (int s0 = 0; s0 < S; s0 += G) {
+      SlotBins<S, G> cur;
+      cur.load(pi, pj, m, lane, s0);
 #pragma unroll
-        for (int k = 0; k < DB; ++k) {
-          const float2 x = (k % 2 == 0) ? xs : xd;                      // eq. (6) order
-          a[k] += w[k] * x.x;
-          b[k] += w[k] * x.y;
+      for (int g = 0; g < G; ++g) {
+        const int s = s0 + g, f = lane + kGroup * s;
+        lo[s] = smooth_step(lo[s], cur.il[g], cur.jl[g], alpha, beta);
+        hi[s] = smooth_step(hi[s], cur.ih[g], cur.jh[g], alpha, beta);
+        if (owns_bin<S>(f, m)) {
+          const float2 el = phat_pair(lo[s]), eh = phat_pair(hi[s]);
+          const float2 xs = cadd(el, eh), xd = csub(el, eh);            // eq. (8)
+          const float* w = pf + f * PW;
+#pragma unroll
+          for (int k = 0; k < DB; ++k) {
+            const float2 x = (k % 2 == 0) ? xs : xd;                      // eq. (6) order
+            a[k] += w[k] * x.x;
+            b[k] += w[k] * x.y;
+          }
         }
       }
+      if (S > G) __builtin_amdgcn_sched_barrier(0);
     }
-    if (lane == 0) {
-      ce = smooth_step(ce, xi[m], xj[m], alpha, beta);
-      const float2 ec = phat_pair(ce);
+    {
+      // centre bin: every lane keeps the same R, lane 0 alone adds it; it
+      // meets the symmetric basis vectors only
+      ce = smooth_step(ce, cc.ci, cc.cj, alpha, beta);
+      float2 ec = phat_pair(ce);
+      ec = lane == 0 ? ec : make_float2(0.f, 0.f);
       const float* w = pf + m * PW;
 #pragma unroll
-      for (int k = 0; k < DB; k += 2) {                                 // centre bin: symmetric k only
+      for (int k = 0; k < DB; k += 2) {
         a[k] += w[k] * ec.x;
         b[k] += w[k] * ec.y;
       }
     }
     // sum the coefficients over the pair's 16 lanes; every lane ends with z
 #pragma unroll
-    for (int off = kGroup / 2; off > 0; off >>= 1)
-#pragma unroll
-      for (int k = 0; k < DB; ++k) {
-        a[k] += __shfl_xor(a[k], off, kGroup);
-        b[k] += __shfl_xor(b[k], off, kGroup);
-      }
+    for (int k = 0; k < DB; ++k) {
+      a[k] = row_sum16(a[k]);
+      b[k] = row_sum16(b[k]);
+    }
     // expansion to the lags of this lane and first-index argmax
     float y[kMaxLagSlots];
     float best = -3.4e38f;
     int bi = I;
 #pragma unroll
     for (int q = 0; q < kMaxLagSlots; ++q) {
-      const int ii = lane + kGroup * q;
       y[q] = 0.f;
-      if (ii < I) {
-        const float* dr = dc + ii * 2 * D;
+      if (q < nq) {
+        const int ii = lane + kGroup * q;
+        const float* dr = dc + (ii < I ? ii : I - 1) * DW;             // rows past I are masked below
         float v = 0.f;
 #pragma unroll
-        for (int k = 0; k < DB; ++k)
-          if (k < D) v += dr[2 * k] * a[k] + dr[2 * k + 1] * b[k];
+        for (int k = 0; k < DB; ++k) v += dr[2 * k] * a[k] + dr[2 * k + 1] * b[k];
         y[q] = v;
-        if (v > best) { best = v; bi = ii; }
+        const bool take = ii < I && v > best;
+        best = take ? v : best;
+        bi = take ? ii : bi;
       }
     }
-#pragma unroll
-    for (int off = kGroup / 2; off > 0; off >>= 1) {
-      const float ov = __shfl_xor(best, off, kGroup);
-      const int oi = __shfl_xor(bi, off, kGroup);
-      if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
-    }
+    row_argmax16(best, bi);
     const int64_t row = t * P + p;
     if (tau) {
       // neighbours of the maximum for the quadratic refinement
@@ -286,6 +428,11 @@ __global__ __launch_bounds__(kThreads) void smooth_fcc_kernel(
   }
 }
 
+// pass 3: padded basis rows [N/4 + 1][Dfold + 1] and dictionary rows [I][2 (Dfold + 1)]
+size_t smooth_lds_bytes(const SmoothArgs& a) {
+  return sizeof(float) * (size_t(a.N / 4 + 1) * (a.Dfold + 1) + size_t(a.I) * 2 * (a.Dfold + 1));
+}
+
 template <int S>
 hipError_t launch_s(const SmoothArgs& a, const Chunking& ch) {
   const int groups = (a.P + kPairsPerBlock - 1) / kPairsPerBlock;
@@ -301,7 +448,7 @@ hipError_t launch_s(const SmoothArgs& a, const Chunking& ch) {
                      a.scratch, PF, ch.count, beta_len);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const size_t lds = sizeof(float) * (size_t(a.N / 4 + 1) * (a.Dfold + 1) + size_t(a.I) * 2 * a.D);
+  const size_t lds = smooth_lds_bytes(a);
   const unsigned blocks = (unsigned)(ch.count * groups);
   const float inv_r = 1.f / (float)a.r;
 #define FCC_SMOOTH_FCC(DB)                                                                                   \
@@ -341,7 +488,7 @@ size_t smooth_scratch_bytes(int64_t T, int P, int N) {
 }
 
 bool smooth_supported(const SmoothArgs& a) {
-  const size_t lds = sizeof(float) * (size_t(a.N / 4 + 1) * (a.Dfold + 1) + size_t(a.I) * 2 * a.D);
+  const size_t lds = smooth_lds_bytes(a);
   return a.N >= 16 && a.N <= 2048 && a.I <= kGroup * kMaxLagSlots && a.Dfold >= a.D &&
          (a.Dfold == 4 || a.Dfold == 8 || a.Dfold == 12 || a.Dfold == 16 || a.Dfold == 24 || a.Dfold == 32) &&
          lds <= 64 * 1024 && a.alpha > 0.f && a.alpha <= 1.f;

@@ -146,6 +146,12 @@ def _smoothed_ref(x, N, hop, tau_max, D, r, alpha):
     dict(kind="cfg2", seconds=2.0, N=512, hop=128, tau_max=0, D=11, r=1, alpha=0.1),
     dict(kind="cfg5", seconds=1.0, N=512, hop=128, tau_max=0, D=5, r=2, alpha=0.3),
     dict(kind="small", seconds=0.2, N=32, hop=16, tau_max=3, D=4, r=2, alpha=0.2),
+    # every slot count per lane (N/64) and the wide bases, which load a frame in groups
+    dict(kind="rand", M=4, seconds=0.3, N=128, hop=64, tau_max=6, D=6, r=2, alpha=0.1),
+    dict(kind="rand", M=3, seconds=0.3, N=256, hop=128, tau_max=14, D=30, r=2, alpha=0.4),
+    dict(kind="rand", M=3, seconds=1.0, N=1024, hop=512, tau_max=12, D=20, r=1, alpha=0.2),
+    dict(kind="rand", M=2, seconds=1.5, N=2048, hop=1024, tau_max=20, D=13, r=1, alpha=0.3),
+    dict(kind="rand", M=3, seconds=0.5, N=512, hop=256, tau_max=10, D=17, r=1, alpha=0.25),
 ])
 def test_smoothed_matches_oracle(torch, fcc, case):
     _say(f"smoothed {case}")
@@ -153,6 +159,9 @@ def test_smoothed_matches_oracle(torch, fcc, case):
         x, xyz, fs = _two_mic(1000 + case["D"], seconds=case["seconds"]), PAIR_15CM, 16000.0
     elif case["kind"] == "small":
         x, xyz, fs = random_signals(1100, 4, int(16000 * case["seconds"])), circular_array(4, 0.02), 16000.0
+    elif case["kind"] == "rand":
+        M = case["M"]
+        x, xyz, fs = random_signals(1200 + case["N"], M, int(16000 * case["seconds"])), circular_array(M, 0.05), 16000.0
     else:
         rec = make_recording(2 if case["kind"] == "cfg2" else 5, seconds=case["seconds"])
         x, xyz, fs = rec.x, rec.mic_xyz, rec.fs
