@@ -69,10 +69,10 @@ struct BinPtrs {
 };
 
 // Slot group of one frame, branch-free: bins f and N/2 - f of microphones i
-// and j for slots s0 .. s0 + G - 1 of a lane.  Large N loads and consumes a
-// frame in groups of at most 8 slots so that the loads in flight stay within
-// the register file.
-constexpr int kSlotGroup = 8;
+// and j for slots s0 .. s0 + G - 1 of a lane.  The FCC pass (and the local
+// scan for large N) loads and consumes a frame in groups of at most 4 slots,
+// so that the loads in flight leave registers for three waves per SIMD.
+constexpr int kSlotGroup = 4;
 
 template <int S, int G>
 struct SlotBins {
@@ -112,9 +112,12 @@ struct CentreBin {
   }
 };
 
-__device__ __forceinline__ float2 smooth_step(float2 R, float2 a, float2 b, float alpha, float beta) {
-  const float2 c = cmul_conj(a, b);
-  return make_float2(beta * R.x + alpha * c.x, beta * R.y + alpha * c.y);
+// Inside passes 1 and 3 the recursion runs on Q = R / alpha:
+//   Q(t) = beta Q(t - 1) + X_i(t) X_j(t)^*,
+// one multiply and two fused multiply-adds per component.  The PHAT R / |R|
+// is the same for Q; scratch and the caller's state keep R itself.
+__device__ __forceinline__ float2 smooth_step(float2 Q, float2 a, float2 b, float beta) {
+  return make_float2(fmaf(a.x, b.x, fmaf(a.y, b.y, beta * Q.x)), fmaf(a.y, b.x, fmaf(-a.x, b.y, beta * Q.y)));
 }
 
 __device__ __forceinline__ float2 phat_pair(float2 R) {
@@ -176,6 +179,8 @@ __device__ __forceinline__ int64_t xcd_linear_block() {
   return (int64_t)xcd * per + (xcd < extra ? xcd : extra) + local;
 }
 
+__device__ __forceinline__ float2 cscale(float2 v, float s) { return make_float2(v.x * s, v.y * s); }
+
 // state index of bin b of pair p
 __device__ __forceinline__ int64_t sidx(int p, int b, int F) { return (int64_t)p * F + b; }
 
@@ -199,7 +204,7 @@ __global__ __launch_bounds__(kThreads) void smooth_local_kernel(
   const int64_t t0 = c * clen, t1 = t0 + clen < T ? t0 + clen : T;
   const int64_t stride = (int64_t)M * NH;
   BinPtrs pi(spec + (t0 * M + i) * NH, NH, lane), pj(spec + (t0 * M + j) * NH, NH, lane);
-  if constexpr (S <= kSlotGroup) {
+  if constexpr (S <= 8) {
     // whole frames fit: keep the next frame's loads in flight during this one
     SlotBins<S, S> nxt, cur;
     CentreBin cn, cc;
@@ -218,10 +223,10 @@ __global__ __launch_bounds__(kThreads) void smooth_local_kernel(
       }
 #pragma unroll
       for (int s = 0; s < S; ++s) {
-        lo[s] = smooth_step(lo[s], cur.il[s], cur.jl[s], alpha, beta);
-        hi[s] = smooth_step(hi[s], cur.ih[s], cur.jh[s], alpha, beta);
+        lo[s] = smooth_step(lo[s], cur.il[s], cur.jl[s], beta);
+        hi[s] = smooth_step(hi[s], cur.ih[s], cur.jh[s], beta);
       }
-      ce = smooth_step(ce, cc.ci, cc.cj, alpha, beta);
+      ce = smooth_step(ce, cc.ci, cc.cj, beta);
     }
   } else {
     for (int64_t t = t0; t < t1; ++t, pi.advance(stride), pj.advance(stride)) {
@@ -231,14 +236,14 @@ __global__ __launch_bounds__(kThreads) void smooth_local_kernel(
         cur.load(pi, pj, m, lane, s0);
 #pragma unroll
         for (int g = 0; g < kSlotGroup; ++g) {
-          lo[s0 + g] = smooth_step(lo[s0 + g], cur.il[g], cur.jl[g], alpha, beta);
-          hi[s0 + g] = smooth_step(hi[s0 + g], cur.ih[g], cur.jh[g], alpha, beta);
+          lo[s0 + g] = smooth_step(lo[s0 + g], cur.il[g], cur.jl[g], beta);
+          hi[s0 + g] = smooth_step(hi[s0 + g], cur.ih[g], cur.jh[g], beta);
         }
         __builtin_amdgcn_sched_barrier(0);
       }
       CentreBin cc;
       cc.load(pi, pj, m, lane);
-      ce = smooth_step(ce, cc.ci, cc.cj, alpha, beta);
+      ce = smooth_step(ce, cc.ci, cc.cj, beta);
     }
   }
   float2* out = scratch + c * (int64_t)P * F;
@@ -246,11 +251,11 @@ __global__ __launch_bounds__(kThreads) void smooth_local_kernel(
   for (int s = 0; s < S; ++s) {
     const int f = lane + kGroup * s;
     if (owns_bin<S>(f, m)) {
-      out[sidx(p, f, F)] = lo[s];
-      out[sidx(p, NH - f, F)] = hi[s];
+      out[sidx(p, f, F)] = cscale(lo[s], alpha);
+      out[sidx(p, NH - f, F)] = cscale(hi[s], alpha);
     }
   }
-  if (lane == 0) out[sidx(p, m, F)] = ce;
+  if (lane == 0) out[sidx(p, m, F)] = cscale(ce, alpha);
 }
 
 // ---- pass 2: carries across chunks, in place ------------------------------
@@ -259,18 +264,59 @@ __global__ void smooth_carry_kernel(const float2* __restrict__ state, float2* __
                                     int64_t PF, int64_t count, float beta_len) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= PF) return;
+  // The local sums do not depend on the carry: read a run of them before
+  // writing the carries back in their place.
+  constexpr int kRun = 8;
   float2 st = state[e];
-  for (int64_t c = 0; c < count; ++c) {
-    float2* slot = scratch + c * PF + e;
-    const float2 local = c + 1 < count ? *slot : make_float2(0.f, 0.f);
-    *slot = st;
-    st = make_float2(beta_len * st.x + local.x, beta_len * st.y + local.y);
+  for (int64_t c0 = 0; c0 < count; c0 += kRun) {
+    float2 local[kRun];
+#pragma unroll
+    for (int u = 0; u < kRun; ++u) {
+      const int64_t c = c0 + u;
+      local[u] = c + 1 < count ? scratch[c * PF + e] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int u = 0; u < kRun; ++u) {
+      const int64_t c = c0 + u;
+      if (c < count) {
+        scratch[c * PF + e] = st;
+        st = make_float2(beta_len * st.x + local[u].x, beta_len * st.y + local[u].y);
+      }
+    }
   }
 }
 
 // ---- pass 3: rerun each chunk from its carry and evaluate FCC --------------
+
+// Advance the recursion of slots s0 .. s0 + G - 1 by one frame and add their
+// PHAT-weighted, folded bins (eq. 8) to the partial coefficients (eq. 9),
+// symmetric and antisymmetric basis vectors alternating as in eq. (6).
+template <int S, int G, int DB>
+__device__ __forceinline__ void project_group(const SlotBins<S, G>& cur, int s0, float2 (&lo)[S], float2 (&hi)[S],
+                                              float (&a)[DB], float (&b)[DB], const float* pf, int lane, int m,
+                                              float beta) {
+  constexpr int PW = DB + 1;
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    const int s = s0 + g, f = lane + kGroup * s;
+    lo[s] = smooth_step(lo[s], cur.il[g], cur.jl[g], beta);
+    hi[s] = smooth_step(hi[s], cur.ih[g], cur.jh[g], beta);
+    if (owns_bin<S>(f, m)) {
+      const float2 el = phat_pair(lo[s]), eh = phat_pair(hi[s]);
+      const float2 xs = cadd(el, eh), xd = csub(el, eh);
+      const float* w = pf + f * PW;
+#pragma unroll
+      for (int k = 0; k < DB; ++k) {
+        const float2 x = (k % 2 == 0) ? xs : xd;
+        a[k] += w[k] * x.x;
+        b[k] += w[k] * x.y;
+      }
+    }
+  }
+}
+
 template <int S, int DB>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(S <= 8 && DB <= 12 ? 2 : 1))) void smooth_fcc_kernel(
+__global__ __launch_bounds__(kThreads) void smooth_fcc_kernel(
     const float2* __restrict__ spec, int64_t T, int M, int P, int N, int I, int D, int lag0, float inv_r,
     int64_t clen, int groups, const uint8_t* __restrict__ pairs, float alpha,
     const float* __restrict__ pfold /*[N/4 + 1][DB]*/, const float* __restrict__ dict /*[I][2D]*/,
@@ -297,7 +343,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(S <= 8
   const bool active = pq < P;                     // idle groups mirror pair 0 so every shuffle is uniform
   const int p = active ? pq : 0;
   const int i = pairs[2 * p], j = pairs[2 * p + 1];
-  const float beta = 1.f - alpha;
+  const float beta = 1.f - alpha, inv_alpha = 1.f / alpha;
   const float2* in = scratch + c * (int64_t)P * F;
   float2 lo[S], hi[S], ce = make_float2(0.f, 0.f);
 #pragma unroll
@@ -305,51 +351,24 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(S <= 8
     const int f = lane + kGroup * s;
     lo[s] = hi[s] = make_float2(0.f, 0.f);
     if (f < m) {
-      lo[s] = in[sidx(p, f, F)];
-      hi[s] = in[sidx(p, NH - f, F)];
+      lo[s] = cscale(in[sidx(p, f, F)], inv_alpha);
+      hi[s] = cscale(in[sidx(p, NH - f, F)], inv_alpha);
     }
   }
-  if (lane == 0) ce = in[sidx(p, m, F)];
+  if (lane == 0) ce = cscale(in[sidx(p, m, F)], inv_alpha);
 
   const int64_t t0 = c * clen, t1 = t0 + clen < T ? t0 + clen : T;
   const int nq = (I + kGroup - 1) / kGroup;      // lag slots in use, uniform
   const int64_t stride = (int64_t)M * NH;
   BinPtrs pi(spec + (t0 * M + i) * NH, NH, lane), pj(spec + (t0 * M + j) * NH, NH, lane);
-  constexpr int kGroupMax = DB <= 12 ? kSlotGroup : kSlotGroup / 2;   // wide bases hold more weights per slot
-  constexpr int G = S < kGroupMax ? S : kGroupMax;
-  for (int64_t t = t0; t < t1; ++t, pi.advance(stride), pj.advance(stride)) {
-    CentreBin cc;
-    cc.load(pi, pj, m, lane);
-    float a[DB], b[DB];
-#pragma unroll
-    for (int k = 0; k < DB; ++k) a[k] = b[k] = 0.f;
-#pragma unroll
-    for (int s0 = 0; s0 < S; s0 += G) {
-      SlotBins<S, G> cur;
-      cur.load(pi, pj, m, lane, s0);
-#pragma unroll
-      for (int g = 0; g < G; ++g) {
-        const int s = s0 + g, f = lane + kGroup * s;
-        lo[s] = smooth_step(lo[s], cur.il[g], cur.jl[g], alpha, beta);
-        hi[s] = smooth_step(hi[s], cur.ih[g], cur.jh[g], alpha, beta);
-        if (owns_bin<S>(f, m)) {
-          const float2 el = phat_pair(lo[s]), eh = phat_pair(hi[s]);
-          const float2 xs = cadd(el, eh), xd = csub(el, eh);            // eq. (8)
-          const float* w = pf + f * PW;
-#pragma unroll
-          for (int k = 0; k < DB; ++k) {
-            const float2 x = (k % 2 == 0) ? xs : xd;                      // eq. (6) order
-            a[k] += w[k] * x.x;
-            b[k] += w[k] * x.y;
-          }
-        }
-      }
-      if (S > G) __builtin_amdgcn_sched_barrier(0);
-    }
+  float a[DB], b[DB];
+  CentreBin cc;
+  // centre bin, sums over the pair's lanes, expansion, argmax and stores of frame t
+  auto frame_tail = [&](int64_t t) {
     {
       // centre bin: every lane keeps the same R, lane 0 alone adds it; it
       // meets the symmetric basis vectors only
-      ce = smooth_step(ce, cc.ci, cc.cj, alpha, beta);
+      ce = smooth_step(ce, cc.ci, cc.cj, beta);
       float2 ec = phat_pair(ce);
       ec = lane == 0 ? ec : make_float2(0.f, 0.f);
       const float* w = pf + m * PW;
@@ -377,7 +396,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(S <= 8
         const float* dr = dc + (ii < I ? ii : I - 1) * DW;             // rows past I are masked below
         float v = 0.f;
 #pragma unroll
-        for (int k = 0; k < DB; ++k) v += dr[2 * k] * a[k] + dr[2 * k + 1] * b[k];
+        for (int k = 0; k < DB; ++k) v = fmaf(dr[2 * k + 1], b[k], fmaf(dr[2 * k], a[k], v));
         y[q] = v;
         const bool take = ii < I && v > best;
         best = take ? v : best;
@@ -413,6 +432,24 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(S <= 8
           if (ii < I) yout[row * I + ii] = y[q];
         }
     }
+  };
+
+  // A frame is loaded and consumed group by group; the loads are not
+  // pipelined across groups: at this register count three waves per SIMD
+  // hide their latency better than a second buffer would.
+  constexpr int G = S < kSlotGroup ? S : kSlotGroup;
+  for (int64_t t = t0; t < t1; ++t, pi.advance(stride), pj.advance(stride)) {
+    cc.load(pi, pj, m, lane);
+#pragma unroll
+    for (int k = 0; k < DB; ++k) a[k] = b[k] = 0.f;
+#pragma unroll
+    for (int s0 = 0; s0 < S; s0 += G) {
+      SlotBins<S, G> cur;
+      cur.load(pi, pj, m, lane, s0);
+      project_group<S, G, DB>(cur, s0, lo, hi, a, b, pf, lane, m, beta);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    frame_tail(t);
   }
   // the last chunk leaves R after the final frame for the next call
   if (active && t1 == T) {
@@ -420,11 +457,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(S <= 8
     for (int s = 0; s < S; ++s) {
       const int f = lane + kGroup * s;
       if (f < m) {
-        state[sidx(p, f, F)] = lo[s];
-        state[sidx(p, NH - f, F)] = hi[s];
+        state[sidx(p, f, F)] = cscale(lo[s], alpha);
+        state[sidx(p, NH - f, F)] = cscale(hi[s], alpha);
       }
     }
-    if (lane == 0) state[sidx(p, m, F)] = ce;
+    if (lane == 0) state[sidx(p, m, F)] = cscale(ce, alpha);
   }
 }
 
@@ -444,7 +481,7 @@ hipError_t launch_s(const SmoothArgs& a, const Chunking& ch) {
   }
   const int64_t PF = (int64_t)a.P * (a.N / 2 + 1);
   const float beta_len = powf(1.f - a.alpha, (float)ch.len);
-  hipLaunchKernelGGL(smooth_carry_kernel, dim3((unsigned)((PF + 255) / 256)), dim3(256), 0, a.stream, a.state,
+  hipLaunchKernelGGL(smooth_carry_kernel, dim3((unsigned)((PF + 63) / 64)), dim3(64), 0, a.stream, a.state,
                      a.scratch, PF, ch.count, beta_len);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
