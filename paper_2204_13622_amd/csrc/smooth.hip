@@ -185,77 +185,138 @@ __device__ __forceinline__ float2 cscale(float2 v, float s) { return make_float2
 __device__ __forceinline__ int64_t sidx(int p, int b, int F) { return (int64_t)p * F + b; }
 
 // ---- pass 1: local scan of every chunk but the last ----------------------
-template <int S>
-__global__ __launch_bounds__(kThreads) void smooth_local_kernel(
-    const float2* __restrict__ spec, int64_t T, int M, int P, int N, int64_t clen, int groups,
-    const uint8_t* __restrict__ pairs, float alpha, float2* __restrict__ scratch) {
-  const int NH = N / 2, m = N / 4, F = NH + 1;
-  const int lane = threadIdx.x % kGroup, grp = threadIdx.x / kGroup;
-  const int64_t v = xcd_linear_block();
-  const int pg = (int)(v % groups);
-  const int64_t c = v / groups;
-  const int p = pg * kPairsPerBlock + grp;
-  if (p >= P) return;                       // no cross-lane work in this pass
-  const int i = pairs[2 * p], j = pairs[2 * p + 1];
-  const float beta = 1.f - alpha;
-  float2 lo[S], hi[S], ce = make_float2(0.f, 0.f);
+// A workgroup owns one chunk, one tile of 64 consecutive spectrum slots and
+// up to 128 consecutive pairs.  Per frame it stages the tile of every
+// microphone in LDS (each spectrum value read once, 16-byte loads, double
+// buffered so the next frame's loads fly during this frame's work); each
+// wave is one group of up to 16 pairs and each lane advances the recursion
+// of its slot for those pairs, stepping through them in their lexicographic
+// (i-major) order.
+constexpr int kTileSlots = 64;
+constexpr int kTileGroups = 16;
+constexpr int kPairsPerLane = 8;
+constexpr int kTilePairs = kTileGroups * kPairsPerLane;
+constexpr int kTileThreads = kTileSlots * kTileGroups;
+constexpr int kTileFetch = 1;                 // float4 per thread per frame: 32 microphones at most
+
+struct TileFetch {
+  float4 v[kTileFetch];
+  // frame t of the tile: [M][64 slots] as float4 (2 slots each), zero past N/2
+  __device__ __forceinline__ void load(const float2* __restrict__ spec, int64_t t, int M, int NH, int slot0) {
+    const int n4 = M * (kTileSlots / 2);
 #pragma unroll
-  for (int s = 0; s < S; ++s) lo[s] = hi[s] = make_float2(0.f, 0.f);
-  const int64_t t0 = c * clen, t1 = t0 + clen < T ? t0 + clen : T;
-  const int64_t stride = (int64_t)M * NH;
-  BinPtrs pi(spec + (t0 * M + i) * NH, NH, lane), pj(spec + (t0 * M + j) * NH, NH, lane);
-  if constexpr (S <= 8) {
-    // whole frames fit: keep the next frame's loads in flight during this one
-    SlotBins<S, S> nxt, cur;
-    CentreBin cn, cc;
-    if (t0 < t1) {
-      nxt.load(pi, pj, m, lane, 0);
-      cn.load(pi, pj, m, lane);
-    }
-    for (int64_t t = t0; t < t1; ++t) {
-      cur = nxt;
-      cc = cn;
-      if (t + 1 < t1) {
-        pi.advance(stride);
-        pj.advance(stride);
-        nxt.load(pi, pj, m, lane, 0);
-        cn.load(pi, pj, m, lane);
-      }
-#pragma unroll
-      for (int s = 0; s < S; ++s) {
-        lo[s] = smooth_step(lo[s], cur.il[s], cur.jl[s], beta);
-        hi[s] = smooth_step(hi[s], cur.ih[s], cur.jh[s], beta);
-      }
-      ce = smooth_step(ce, cc.ci, cc.cj, beta);
-    }
-  } else {
-    for (int64_t t = t0; t < t1; ++t, pi.advance(stride), pj.advance(stride)) {
-#pragma unroll
-      for (int s0 = 0; s0 < S; s0 += kSlotGroup) {
-        SlotBins<S, kSlotGroup> cur;
-        cur.load(pi, pj, m, lane, s0);
-#pragma unroll
-        for (int g = 0; g < kSlotGroup; ++g) {
-          lo[s0 + g] = smooth_step(lo[s0 + g], cur.il[g], cur.jl[g], beta);
-          hi[s0 + g] = smooth_step(hi[s0 + g], cur.ih[g], cur.jh[g], beta);
-        }
-        __builtin_amdgcn_sched_barrier(0);
-      }
-      CentreBin cc;
-      cc.load(pi, pj, m, lane);
-      ce = smooth_step(ce, cc.ci, cc.cj, beta);
+    for (int k = 0; k < kTileFetch; ++k) {
+      const int e = threadIdx.x + kTileThreads * k, m = e / (kTileSlots / 2), sl = slot0 + 2 * (e % (kTileSlots / 2));
+      v[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (e < n4 && sl < NH) v[k] = *reinterpret_cast<const float4*>(spec + ((t * M + m) * NH + sl));
     }
   }
+  __device__ __forceinline__ void store(float4* __restrict__ dst, int M) const {
+    const int n4 = M * (kTileSlots / 2);
+#pragma unroll
+    for (int k = 0; k < kTileFetch; ++k) {
+      const int e = threadIdx.x + kTileThreads * k;
+      if (e < n4) dst[e] = v[k];
+    }
+  }
+};
+
+// One frame for the 16 pair slots of a wave, straight-line: the scalar unit
+// walks (i, j) through the pairs in lexicographic order (clamped to the last
+// pair once the walk leaves the triangle; slots past the wave's pairs are
+// computed and never stored) and every lane reads both operands of a pair
+// from the staged rows.  DC: this lane holds slot 0, the packed (X(0), X(N/2))
+// pair, whose two real bins take componentwise products; those selects are
+// compiled only into the tile that contains slot 0.
+template <bool DC>
+__device__ __forceinline__ void tile_frame(const float2* __restrict__ row /*[M][64]*/, int s, int M, int i0, int j0,
+                                           float beta, bool dc, float2 (&Q)[kPairsPerLane]) {
+  int i = i0, j = j0;
+#pragma unroll
+  for (int q = 0; q < kPairsPerLane; ++q) {
+    const float2 xi = row[i * kTileSlots + s], xj = row[j * kTileSlots + s];
+    if constexpr (DC) {
+      // (a.x b.x, a.y b.y) on the DC lane, a b^* elsewhere
+      const float ay = dc ? 0.f : xi.y, nax = dc ? 0.f : -xi.x, bxy = dc ? xj.y : xj.x;
+      Q[q] = make_float2(fmaf(xi.x, xj.x, fmaf(ay, xj.y, beta * Q[q].x)),
+                         fmaf(xi.y, bxy, fmaf(nax, xj.y, beta * Q[q].y)));
+    } else {
+      Q[q] = smooth_step(Q[q], xi, xj, beta);
+    }
+    // next pair: (i, j + 1), or (i + 1, i + 2) past the end of row i
+    const bool wrap = j + 1 == M;
+    i = wrap ? i + 1 : i;
+    j = wrap ? i + 1 : j + 1;
+    const bool out = i >= M - 1;              // past (M - 2, M - 1): stay there
+    i = out ? M - 2 : i;
+    j = out ? M - 1 : j;
+  }
+}
+
+__global__ __launch_bounds__(kTileThreads) void smooth_local_kernel(
+    const float2* __restrict__ spec, int64_t T, int M, int P, int N, int64_t clen, int tiles, int pblocks,
+    float alpha, float2* __restrict__ scratch) {
+  extern __shared__ float4 stage[];             // [2][M][64 slots]
+  const int NH = N / 2, F = NH + 1;
+  int64_t v = blockIdx.x;
+  const int pb = (int)(v % pblocks);
+  v /= pblocks;
+  const int tile = (int)(v % tiles);
+  const int64_t c = v / tiles;
+  // g: this wave's pair group, uniform (the pair walk below then runs on scalars)
+  const int s = threadIdx.x % kTileSlots, g = __builtin_amdgcn_readfirstlane(threadIdx.x / kTileSlots);
+  const int slot0 = tile * kTileSlots, slot = slot0 + s;
+
+  // pairs [p0, p0 + np) of this wave, and the first of them as (i, j)
+  const int pbase = pb * kTilePairs, pcount = P - pbase < kTilePairs ? P - pbase : kTilePairs;
+  const int per = (pcount + kTileGroups - 1) / kTileGroups;
+  const int p0 = pbase + g * per;
+  int np = P - p0 < per ? P - p0 : per;
+  if (np < 0) np = 0;
+  // row i of the pair triangle holds the M - 1 - i pairs (i, i + 1 .. M - 1)
+  int i0 = 0, rest = p0 < P ? p0 : 0;
+  while (rest >= M - 1 - i0) {
+    rest -= M - 1 - i0;
+    ++i0;
+  }
+  const int j0 = i0 + 1 + rest;
+
+  const float beta = 1.f - alpha;
+  float2 Q[kPairsPerLane];
+#pragma unroll
+  for (int q = 0; q < kPairsPerLane; ++q) Q[q] = make_float2(0.f, 0.f);
+  const int64_t t0 = c * clen, t1 = t0 + clen < T ? t0 + clen : T;
+  const int n4 = M * (kTileSlots / 2);
+  TileFetch fetch;
+  fetch.load(spec, t0, M, NH, slot0);
+  fetch.store(stage, M);
+  __syncthreads();
+  for (int64_t t = t0; t < t1; ++t) {
+    const int buf = (int)((t - t0) & 1);
+    if (t + 1 < t1) fetch.load(spec, t + 1, M, NH, slot0);
+    const float2* row = reinterpret_cast<const float2*>(stage + buf * n4);
+    if (tile == 0)
+      tile_frame<true>(row, s, M, i0, j0, beta, s == 0, Q);
+    else
+      tile_frame<false>(row, s, M, i0, j0, beta, false, Q);
+    if (t + 1 < t1) fetch.store(stage + (buf ^ 1) * n4, M);
+    __syncthreads();
+  }
+
+  if (slot >= NH) return;
   float2* out = scratch + c * (int64_t)P * F;
 #pragma unroll
-  for (int s = 0; s < S; ++s) {
-    const int f = lane + kGroup * s;
-    if (owns_bin<S>(f, m)) {
-      out[sidx(p, f, F)] = cscale(lo[s], alpha);
-      out[sidx(p, NH - f, F)] = cscale(hi[s], alpha);
+  for (int q = 0; q < kPairsPerLane; ++q) {
+    if (q < np) {
+      float2* o = out + (int64_t)(p0 + q) * F;
+      if (slot == 0) {
+        o[0] = make_float2(alpha * Q[q].x, 0.f);
+        o[NH] = make_float2(alpha * Q[q].y, 0.f);
+      } else {
+        o[slot] = cscale(Q[q], alpha);
+      }
     }
   }
-  if (lane == 0) out[sidx(p, m, F)] = cscale(ce, alpha);
 }
 
 // ---- pass 2: carries across chunks, in place ------------------------------
@@ -474,8 +535,10 @@ template <int S>
 hipError_t launch_s(const SmoothArgs& a, const Chunking& ch) {
   const int groups = (a.P + kPairsPerBlock - 1) / kPairsPerBlock;
   if (ch.count > 1) {
-    hipLaunchKernelGGL(smooth_local_kernel<S>, dim3((unsigned)((ch.count - 1) * groups)), dim3(kThreads), 0,
-                       a.stream, a.spec, a.T, a.M, a.P, a.N, ch.len, groups, a.pairs, a.alpha, a.scratch);
+    const int tiles = (a.N / 2 + kTileSlots - 1) / kTileSlots, pblocks = (a.P + kTilePairs - 1) / kTilePairs;
+    const size_t stage = 2 * sizeof(float4) * size_t(a.M) * (kTileSlots / 2);
+    hipLaunchKernelGGL(smooth_local_kernel, dim3((unsigned)((ch.count - 1) * tiles * pblocks)), dim3(kTileThreads),
+                       stage, a.stream, a.spec, a.T, a.M, a.P, a.N, ch.len, tiles, pblocks, a.alpha, a.scratch);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -526,7 +589,8 @@ size_t smooth_scratch_bytes(int64_t T, int P, int N) {
 
 bool smooth_supported(const SmoothArgs& a) {
   const size_t lds = smooth_lds_bytes(a);
-  return a.N >= 16 && a.N <= 2048 && a.I <= kGroup * kMaxLagSlots && a.Dfold >= a.D &&
+  return a.M >= 2 && a.M * (kTileSlots / 2) <= kTileFetch * kTileThreads && a.N >= 16 && a.N <= 2048 &&
+         a.I <= kGroup * kMaxLagSlots && a.Dfold >= a.D &&
          (a.Dfold == 4 || a.Dfold == 8 || a.Dfold == 12 || a.Dfold == 16 || a.Dfold == 24 || a.Dfold == 32) &&
          lds <= 64 * 1024 && a.alpha > 0.f && a.alpha <= 1.f;
 }
