@@ -137,9 +137,14 @@ __device__ __forceinline__ void run_frames(const uint32_t* lds_all, uint32_t* sl
   uint4 pre[kPrefetch];                        // first kPrefetch rounds, in flight
   auto prefetch = [&](int64_t tf) {
     const typename S::T* base = spec + tf * (int64_t)M * NH;
+    if (rounds >= kPrefetch) {                  // every slot in use: no guards
 #pragma unroll
-    for (int u = 0; u < kPrefetch; ++u)
-      if (u < rounds) pre[u] = load4<S>(base + 4 * (lane + 64 * u));
+      for (int u = 0; u < kPrefetch; ++u) pre[u] = load4<S>(base + 4 * (lane + 64 * u));
+    } else {
+#pragma unroll
+      for (int u = 0; u < kPrefetch; ++u)
+        if (u < rounds) pre[u] = load4<S>(base + 4 * (lane + 64 * u));
+    }
   };
   if (t < T) prefetch(t);
 
@@ -211,8 +216,16 @@ __device__ __forceinline__ void run_frames(const uint32_t* lds_all, uint32_t* sl
           acc[kb][ib] = __builtin_amdgcn_mfma_f32_16x16x32_f16(Am[ib] * pk, B, acc[kb][ib], 0, 0, 0);
       }
     };
-    kstep(0, g == 0);
-    for (int s = 1; s < nsteps; ++s) kstep(16 * s, false);
+    if (KB <= 3 && nsteps >= 2) {               // two K steps per trip (nsteps = N/32 is a power of two);
+                                                // wider bases have no registers to spare for it
+      for (int s = 0; s < nsteps; s += 2) {
+        kstep(16 * s, s == 0 && g == 0);
+        kstep(16 * s + 16, false);
+      }
+    } else {
+      kstep(0, g == 0);
+      for (int s = 1; s < nsteps; ++s) kstep(16 * s, false);
+    }
     wave_sync();   // every lane has read the spectra; the slab now takes Y
 
     // ---- expansion: Y_i(tau, j) = sum_k G(tau, k) H_k(i, j) --------------------
