@@ -37,6 +37,8 @@ def parse_args():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--seed", type=int, default=2000)
+    ap.add_argument("--settle", type=float, default=0.3, metavar="SECONDS",
+                    help="untimed steps before any timing so the GPU clocks settle (0 under counter runs)")
     ap.add_argument("--batch-seconds", type=float, default=2.0,
                     help="audio per array in the 256-array batch measurement")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -245,8 +247,14 @@ def main():
 
     plan, T, ws, out = make(args.precision, args.rank)
     P = plan.P
-    # per-kernel averages over their own timed loops (same stream); they run
-    # first, so the GPU's clocks have ramped before the headline measurement
+    step = lambda: plan.tdoa(x, out=out, workspace=ws)  # noqa: E731
+    # let the GPU's clocks settle: untimed steps for --settle seconds before any timing
+    settle_end = time.time() + args.settle
+    while time.time() < settle_end:
+        for _ in range(20):
+            step()
+        torch.cuda.synchronize()
+    # per-kernel averages over their own timed loops (same stream)
     spec_view = ws[:T * plan.info.spectrum_bytes_per_frame].view(
         plan.spectrum_dtype()).view(T, plan.M, plan.N // 2, 2)
     run_stft = lambda: plan.spectra(x, out=spec_view)  # noqa: E731
@@ -257,7 +265,6 @@ def main():
     ms_stft = time_loop(torch, run_stft, args.steps)
     ms_pair = time_loop(torch, run_pair, args.steps)
 
-    step = lambda: plan.tdoa(x, out=out, workspace=ws)  # noqa: E731
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
