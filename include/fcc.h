@@ -247,13 +247,13 @@ fcc_status fcc_doa(fcc_plan plan, const float* d_y, int64_t num_frames, const fl
 
 /* ---- batches of independent arrays ------------------------------------------
  * Many arrays of uneven microphone count, aperture, sample rate, frame size and
- * rank (each with its own plan) in one pass: every array's front end in one
- * persistent launch, and the pair stage of every array in one persistent
- * launch per class of arrays sharing a matrix-core tile shape, with work items
- * (array, block of transforms) and (array, tile of frames) taken from queues.
- * With use_graph the pass is captured once into a graph (per set of buffer
- * pointers) and replayed.  fcc_batch_tune times candidate tile shapes on the
- * given buffers and keeps the fastest.
+ * rank (each with its own plan) in one pass: the front end of every array in
+ * one launch per frame size present (one workgroup per block of transforms),
+ * and the pair stage of every array in one persistent launch per class of
+ * arrays sharing a matrix-core tile shape, with work items (array, tile of
+ * frames) taken from a queue.  With use_graph the pass is captured once into a
+ * graph (per set of buffer pointers) and replayed.  fcc_batch_tune times
+ * candidate pair-stage tile shapes on the given buffers and keeps the fastest.
  * Limits: every plan FP16 or BF16 storage (the same), method FCC, alpha = 1,
  * M <= 16, N >= 32, I <= 48, rank <= 32 (FCC_ERR_UNSUPPORTED otherwise).
  * Plans are copied; num_samples[a] fixes array a's length L_a at creation.
@@ -286,8 +286,8 @@ fcc_status fcc_batch_tdoa(fcc_batch batch, const void* d_image, const float* d_a
 /* Autotuner; synchronises `stream` while timing.  Overwrites d_tdoa. */
 fcc_status fcc_batch_tune(fcc_batch batch, const void* d_image, const float* d_audio, int32_t* d_tdoa,
                           void* d_workspace, hipStream_t stream);
-/* The tile shapes in use: values[0..1] front end (items per queue grab,
- * workgroups per compute unit), then per class (frames per item, wavefronts
+/* The launch shapes in use: values[0] the number of front-end launches (frame
+ * sizes present), values[1] 0, then per class (frames per item, wavefronts
  * per workgroup, workgroups per compute unit); capacity >= 2 + 3 num_classes. */
 fcc_status fcc_batch_tuning(fcc_batch batch, int32_t* values, int32_t capacity);
 

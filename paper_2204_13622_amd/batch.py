@@ -6,7 +6,7 @@
     per_array = batch.split(tdoa)             # [T_a, P_a] views
     batch.tune(audio)                         # pick tile shapes by timing them
 
-The library runs every array's front end in one persistent launch and the
+The library runs the front end in one launch per frame size present and the
 pair stage in one launch per class of arrays sharing a matrix-core tile
 shape, optionally captured once into a graph and replayed; this module only
 allocates the buffers and marshals the calls.
@@ -87,8 +87,8 @@ class Batch:
         return out
 
     def tune(self, audio, out=None):
-        """Times candidate tile shapes on these buffers and keeps the fastest;
-        returns the shapes chosen."""
+        """Times candidate pair-stage tile shapes on these buffers and keeps
+        the fastest; returns the shapes in use."""
         torch = _torch()
         if out is None:
             out = torch.empty(max(self.info.tdoa_count, 1), dtype=torch.int32, device=self.device)
@@ -102,7 +102,7 @@ class Batch:
         v = (ctypes.c_int32 * cap)()
         _lib.check(self._lib.fcc_batch_tuning(self._h, v, cap))
         v = list(v)
-        return {"front_end": {"items_per_grab": v[0], "blocks_per_cu": v[1]},
+        return {"front_end": {"launches": v[0]},
                 "pair_classes": [{"frames_per_item": v[2 + 3 * c], "waves": v[3 + 3 * c],
                                   "blocks_per_cu": v[4 + 3 * c]} for c in range(self.info.num_classes)]}
 

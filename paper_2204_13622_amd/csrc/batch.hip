@@ -1,15 +1,14 @@
 // Many independent arrays of uneven microphone count, aperture, sample rate,
 // frame size and rank in one pass.  Every array keeps its own plan tables
-// (its slice of the batch image) and its own spectra and outputs; the work is
-// cut into items that persistent workgroups take from atomic queues:
-//   - front end: one launch for every array; an item is one block of
-//     transforms (microphone-frames) of one array, handed out in chunks of
-//     consecutive items so overlapping frames meet in the same L1 / L2;
-//     the transform size is dispatched per item;
-//   - pair stage: one launch per class of arrays that share the matrix-core
-//     tile shape (components in blocks of four, lags in tiles of 16); an item
-//     is a tile of consecutive frames of one array, whose tables the
-//     workgroup stages into LDS when the array changes.
+// (its slice of the batch image) and its own spectra and outputs:
+//   - front end: one launch per frame size present, one workgroup per block
+//     of transforms (microphone-frames) of one array; the items of a size are
+//     numbered consecutively and a host-built table maps each to its array;
+//   - pair stage: one persistent launch per class of arrays that share the
+//     matrix-core tile shape (components in blocks of four, lags in tiles of
+//     16); an item is a tile of consecutive frames of one array, taken from
+//     an atomic queue; each workgroup stages the class's item prefix in LDS
+//     once, and the array's tables when the array changes.
 // The queues are counters in the workspace, cleared by a fill kernel, so the
 // whole sequence can be captured in one graph.
 #include "kernels.hpp"
@@ -19,85 +18,102 @@
 namespace fcc {
 namespace {
 
+// Front end, one launch per frame size: one workgroup per block of
+// transforms, exactly as the single-array kernel (tables staged per
+// workgroup, XCD-contiguous order so a frame's 4x overlap with its neighbours
+// is served by one L2); the item's array comes from a table built on the host.
 template <int N, class S>
-__device__ __forceinline__ void stft_item(float2* lds, int& cur_N, const BatchArray& d, const unsigned char* image,
-                                          const float* audio, unsigned char* spec_base, int64_t lblk) {
+__global__ __launch_bounds__(stft_core::kThreads) void batch_stft_kernel(
+    const BatchArray* __restrict__ arrays, const int32_t* __restrict__ item_array, int64_t first_item,
+    const unsigned char* __restrict__ image, const float* __restrict__ audio, unsigned char* __restrict__ spec_base) {
   using Sh = stft_core::StftShape<N>;
-  float2* tw = lds;
-  float2* tw1 = tw + N;
-  float2* tw2 = tw1 + Sh::T1;
-  float2* data = tw2 + Sh::T2;
-  if (cur_N != N) {                 // the tables depend on N only
-    stft_core::load_tables<N>(tw, tw1, tw2, reinterpret_cast<const float2*>(image + d.img_off + d.tab_twiddle));
-    __syncthreads();
-    cur_N = N;
-  }
+  __shared__ float2 tw[N];
+  __shared__ float2 tw1[Sh::T1];
+  __shared__ float2 tw2[Sh::T2];
+  __shared__ float2 data[Sh::FPB * Sh::NHP];
+  constexpr unsigned kXcds = 8;
+  const unsigned nblk = gridDim.x;
+  const unsigned xcd = blockIdx.x % kXcds, local = blockIdx.x / kXcds;
+  const unsigned per = nblk / kXcds, extra = nblk % kXcds;
+  const int64_t it = first_item + (int64_t)(xcd * per + (xcd < extra ? xcd : extra) + local);
+  const BatchArray& d = arrays[item_array[it]];
+  stft_core::load_tables<N>(tw, tw1, tw2, reinterpret_cast<const float2*>(image + d.img_off + d.tab_twiddle));
+  __syncthreads();
   stft_core::transforms<N, S, false>(tw, tw1, tw2, data, audio + d.audio_off, d.L, d.M, d.hop, d.T * d.M,
-                                     reinterpret_cast<typename S::T*>(spec_base + d.spec_off), lblk);
+                                     reinterpret_cast<typename S::T*>(spec_base + d.spec_off), it - d.stft_first);
 }
 
-template <class S>
-__global__ __launch_bounds__(stft_core::kThreads) void batch_stft_kernel(
-    const BatchArray* __restrict__ arrays, int n, int64_t total_items, int chunk,
-    const unsigned char* __restrict__ image, const float* __restrict__ audio, unsigned char* __restrict__ spec_base,
-    int* __restrict__ queue) {
-  extern __shared__ float2 lds2[];
-  __shared__ long long item_sh;
-  int cur_N = 0;
-  for (;;) {
-    if (threadIdx.x == 0) item_sh = (long long)atomicAdd(queue, 1) * chunk;
-    __syncthreads();
-    const int64_t first = item_sh;
-    __syncthreads();                                   // read before thread 0 takes the next chunk
-    if (first >= total_items) break;                   // the same for every thread of the block
-    const int64_t last = first + chunk < total_items ? first + chunk : total_items;
-    for (int64_t it = first; it < last; ++it) {
-      int lo = 0, hi = n - 1;                          // last array whose first item is <= it
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (arrays[mid].stft_first <= it) lo = mid;
-        else hi = mid - 1;
-      }
-      const BatchArray& d = arrays[lo];
-      const int64_t lblk = it - d.stft_first;
-#define FCC_ITEM(NN)                                                    \
-  case NN:                                                              \
-    stft_item<NN, S>(lds2, cur_N, d, image, audio, spec_base, lblk);    \
-    break;
-      switch (d.N) {
-        FCC_ITEM(16) FCC_ITEM(32) FCC_ITEM(64) FCC_ITEM(128) FCC_ITEM(256) FCC_ITEM(512) FCC_ITEM(1024)
-        FCC_ITEM(2048)
-      }
-#undef FCC_ITEM
-      __syncthreads();                                 // the scratch is reused by the next item
-    }
+// Tiles of ft frames of member c start at item first[c]; first[n] is the
+// class's item count.  Computed once per workgroup by wavefront 0: each lane
+// sums a run of members, a 64-lane scan gives the runs' offsets.
+__device__ __forceinline__ void tile_prefix(const BatchArray* __restrict__ arrays, const int32_t* __restrict__ members,
+                                            int n, int ft, int* __restrict__ first) {
+  if (threadIdx.x >= 64) return;
+  const int lane = threadIdx.x, run = (n + 63) / 64, c0 = lane * run, c1 = c0 + run < n ? c0 + run : n;
+  int sum = 0;
+  for (int c = c0; c < c1; ++c) sum += (int)((arrays[members[c]].T + ft - 1) / ft);
+  int incl = sum;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int v = __shfl_up(incl, off, 64);
+    if (lane >= off) incl += v;
   }
+  int at = incl - sum;                           // items before this lane's run
+  for (int c = c0; c < c1; ++c) {
+    first[c] = at;
+    at += (int)((arrays[members[c]].T + ft - 1) / ft);
+  }
+  if (lane == 63) first[n] = incl;
 }
 
 template <class S, int KB, int TT, int kWaves>
 __global__ __launch_bounds__(64 * kWaves, 2) void batch_pair_kernel(
     const BatchArray* __restrict__ arrays, const int32_t* __restrict__ members, int n_members, int ft,
     const unsigned char* __restrict__ image, const unsigned char* __restrict__ spec_base,
-    int32_t* __restrict__ tdoa_base, int* __restrict__ queue, int slab_words) {
+    int32_t* __restrict__ tdoa_base, int* __restrict__ queue, int slab_words, int prefix_off) {
   extern __shared__ uint32_t lds_all[];
   __shared__ int item_sh[3];
   const int wave = threadIdx.x >> 6;
+  // the item prefix lives past the largest table head and the slabs; prefix_off < 0: the class is
+  // too large to stage it and thread 0 walks the member list instead
+  const bool staged = prefix_off >= 0;
+  int* first = reinterpret_cast<int*>(lds_all + (staged ? prefix_off : 0));
+  if (staged) {
+    tile_prefix(arrays, members, n_members, ft, first);
+    __syncthreads();
+  }
   int cur = -1;
   for (;;) {
     if (threadIdx.x == 0) {
-      // item -> (array, first frame, end frame): walk the class's arrays
       int rem = atomicAdd(queue, 1), a = -1, t0 = 0, t1 = 0;
-      for (int c = 0; c < n_members; ++c) {
-        const int m = members[c];
-        const int64_t T = arrays[m].T;
-        const int tiles = (int)((T + ft - 1) / ft);
-        if (rem < tiles) {
-          a = m;
-          t0 = rem * ft;
+      if (staged) {
+        // item -> member: last c with first[c] <= rem
+        if (rem < first[n_members]) {
+          int lo = 0, hi = n_members - 1;
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (first[mid] <= rem) lo = mid;
+            else hi = mid - 1;
+          }
+          a = members[lo];
+          const int64_t T = arrays[a].T;
+          t0 = (rem - first[lo]) * ft;
           t1 = (int)(t0 + ft < T ? t0 + ft : T);
-          break;
         }
-        rem -= tiles;
+      } else {
+        // walk the class's arrays
+        for (int c = 0; c < n_members; ++c) {
+          const int m = members[c];
+          const int64_t T = arrays[m].T;
+          const int tiles = (int)((T + ft - 1) / ft);
+          if (rem < tiles) {
+            a = m;
+            t0 = rem * ft;
+            t1 = (int)(t0 + ft < T ? t0 + ft : T);
+            break;
+          }
+          rem -= tiles;
+        }
       }
       item_sh[0] = a;
       item_sh[1] = t0;
@@ -135,26 +151,16 @@ int num_cus() {
   return cus;
 }
 
-size_t stft_lds_for(int N) {
-  switch (N) {
-    case 16: return sizeof(float2) * stft_core::StftShape<16>::lds_float2;
-    case 32: return sizeof(float2) * stft_core::StftShape<32>::lds_float2;
-    case 64: return sizeof(float2) * stft_core::StftShape<64>::lds_float2;
-    case 128: return sizeof(float2) * stft_core::StftShape<128>::lds_float2;
-    case 256: return sizeof(float2) * stft_core::StftShape<256>::lds_float2;
-    case 512: return sizeof(float2) * stft_core::StftShape<512>::lds_float2;
-    case 1024: return sizeof(float2) * stft_core::StftShape<1024>::lds_float2;
-    case 2048: return sizeof(float2) * stft_core::StftShape<2048>::lds_float2;
-  }
-  return 0;
-}
-
 template <class S, int KB, int TT, int WV>
 hipError_t launch_pair_class(const BatchRun& r, const BatchClass& c, int ft, int blocks_per_cu) {
   if (ft < 1 || blocks_per_cu < 1) return hipErrorInvalidValue;
   auto k = batch_pair_kernel<S, KB, TT, WV>;
-  const size_t lds = sizeof(uint32_t) * (size_t(c.head_words_max) + size_t(WV) * c.slab_words_max);
-  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  const size_t base_words = size_t(c.head_words_max) + size_t(WV) * c.slab_words_max;
+  if (sizeof(uint32_t) * base_words > 160 * 1024) return hipErrorInvalidValue;
+  // stage the class's item prefix when it fits beside the tables and slabs
+  const size_t prefix_words = size_t(c.member_count) + 1;
+  const bool staged = sizeof(uint32_t) * (base_words + prefix_words) <= 160 * 1024;
+  const size_t lds = sizeof(uint32_t) * (base_words + (staged ? prefix_words : 0));
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -165,7 +171,8 @@ hipError_t launch_pair_class(const BatchRun& r, const BatchClass& c, int ft, int
   if (blocks > items) blocks = items;
   if (blocks < 1) return hipSuccess;
   hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * WV), lds, r.stream, r.arrays, r.members + c.member_first,
-                     c.member_count, ft, r.image, r.spec, r.tdoa, r.queue + 1 + c.index, c.slab_words_max);
+                     c.member_count, ft, r.image, r.spec, r.tdoa, r.queue + 1 + c.index, c.slab_words_max,
+                     staged ? int(base_words) : -1);
   return hipGetLastError();
 }
 
@@ -229,23 +236,41 @@ int64_t BatchClass::items(int ft) const {
   return n;
 }
 
-hipError_t launch_batch_stft(const BatchRun& r, const StftTuning& t) {
-  if (r.stft_items == 0) return hipSuccess;
-  if (t.chunk < 1 || t.blocks_per_cu < 1) return hipErrorInvalidValue;
-  size_t lds = 0;
-  for (int N : r.sizes) lds = stft_lds_for(N) > lds ? stft_lds_for(N) : lds;
-  auto k = r.precision == FCC_BF16 ? batch_stft_kernel<SpecBF16> : batch_stft_kernel<SpecF16>;
-  if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+namespace {
+
+template <int N, class S>
+hipError_t launch_stft_range(const BatchRun& r, int64_t first, int64_t count) {
+  hipLaunchKernelGGL((batch_stft_kernel<N, S>), dim3((unsigned)count), dim3(stft_core::kThreads), 0, r.stream,
+                     r.arrays, r.item_array, first, r.image, r.audio, r.spec);
+  return hipGetLastError();
+}
+
+template <class S>
+hipError_t launch_stft_size(const BatchRun& r, int N, int64_t first, int64_t count) {
+  switch (N) {
+    case 16: return launch_stft_range<16, S>(r, first, count);
+    case 32: return launch_stft_range<32, S>(r, first, count);
+    case 64: return launch_stft_range<64, S>(r, first, count);
+    case 128: return launch_stft_range<128, S>(r, first, count);
+    case 256: return launch_stft_range<256, S>(r, first, count);
+    case 512: return launch_stft_range<512, S>(r, first, count);
+    case 1024: return launch_stft_range<1024, S>(r, first, count);
+    case 2048: return launch_stft_range<2048, S>(r, first, count);
+  }
+  return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+hipError_t launch_batch_stft(const BatchRun& r) {
+  for (const BatchStftRange& g : r.stft_ranges) {
+    if (g.count <= 0) continue;
+    if (g.count > 0x7fffffff) return hipErrorInvalidValue;
+    const hipError_t e = r.precision == FCC_BF16 ? launch_stft_size<SpecBF16>(r, g.N, g.first, g.count)
+                                                 : launch_stft_size<SpecF16>(r, g.N, g.first, g.count);
     if (e != hipSuccess) return e;
   }
-  const int64_t chunks = (r.stft_items + t.chunk - 1) / t.chunk;
-  int64_t blocks = (int64_t)num_cus() * t.blocks_per_cu;
-  if (blocks > chunks) blocks = chunks;
-  hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(stft_core::kThreads), lds, r.stream, r.arrays, r.n_arrays,
-                     r.stft_items, t.chunk, r.image, r.audio, r.spec, r.queue);
-  return hipGetLastError();
+  return hipSuccess;
 }
 
 hipError_t launch_batch_pair(const BatchRun& r, const BatchClass& c, const PairTuning& t) {

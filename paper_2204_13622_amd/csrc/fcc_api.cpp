@@ -26,12 +26,12 @@ struct fcc_batch_s {
   std::vector<int32_t> members;
   std::vector<fcc::BatchClass> classes;
   std::vector<unsigned char> image;
-  size_t arrays_off = 0, members_off = 0;
+  size_t arrays_off = 0, members_off = 0, items_off = 0;
   int64_t audio_floats = 0, tdoa_count = 0, stft_items = 0;
   size_t spec_bytes = 0, queue_off = 0, workspace_bytes = 0;
-  std::vector<int> sizes;
+  std::vector<fcc::BatchStftRange> stft_ranges;   // front-end items, grouped by frame size
+  std::vector<int32_t> item_array;                // array of every front-end item
   fcc_precision precision = FCC_FP16;
-  fcc::StftTuning stft_tuning;
   std::vector<fcc::PairTuning> pair_tuning;
   hipStream_t capture_stream = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -576,8 +576,8 @@ fcc::BatchRun batch_run(fcc_batch b, const void* d_image, const float* d_audio, 
   r.spec = static_cast<unsigned char*>(d_ws);
   r.tdoa = d_tdoa;
   r.queue = reinterpret_cast<int*>(static_cast<unsigned char*>(d_ws) + b->queue_off);
-  r.stft_items = b->stft_items;
-  r.sizes = b->sizes;
+  r.item_array = reinterpret_cast<const int32_t*>(img + b->items_off);
+  r.stft_ranges = b->stft_ranges;
   r.precision = b->precision;
   r.stream = stream;
   return r;
@@ -586,7 +586,7 @@ fcc::BatchRun batch_run(fcc_batch b, const void* d_image, const float* d_audio, 
 hipError_t batch_enqueue(fcc_batch b, const fcc::BatchRun& r) {
   hipError_t e = fcc::launch_fill_zero(reinterpret_cast<float*>(r.queue), int64_t(1 + b->classes.size()), r.stream);
   if (e != hipSuccess) return e;
-  if ((e = fcc::launch_batch_stft(r, b->stft_tuning)) != hipSuccess) return e;
+  if ((e = fcc::launch_batch_stft(r)) != hipSuccess) return e;
   for (size_t c = 0; c < b->classes.size(); ++c)
     if ((e = fcc::launch_batch_pair(r, b->classes[c], b->pair_tuning[c])) != hipSuccess) return e;
   return hipSuccess;
@@ -646,16 +646,32 @@ fcc_status fcc_batch_create(const fcc_plan* plans, int32_t num_arrays, const int
     d.tab_pairs = int64_t(p.layout.pairs);
     d.tab_prow16 = int64_t(p.layout.prow16);
     d.tab_gexp = int64_t(p.layout.gexp);
-    d.stft_first = b->stft_items;
-    const int fpb = fcc::stft_transforms_per_block(p.N);
-    b->stft_items += (d.T * d.M + fpb - 1) / fpb;
     b->audio_floats += int64_t(p.M) * num_samples[a];
     b->tdoa_count += d.T * p.P;
     spec += batch_align(size_t(d.T) * p.M * (p.N / 2) * p.spec_elem);
     img += batch_align(p.layout.total);
     b->arrays.push_back(d);
     by_shape[{kb, tt}].push_back(a);
-    if (std::find(b->sizes.begin(), b->sizes.end(), p.N) == b->sizes.end()) b->sizes.push_back(p.N);
+  }
+  // front-end items: blocks of transforms, numbered frame size by frame size
+  // (one launch per size), array by array within a size
+  std::vector<int> sizes;
+  for (const fcc::BatchArray& d : b->arrays)
+    if (std::find(sizes.begin(), sizes.end(), d.N) == sizes.end()) sizes.push_back(d.N);
+  std::sort(sizes.begin(), sizes.end());
+  for (int N : sizes) {
+    fcc::BatchStftRange g{N, b->stft_items, 0};
+    const int fpb = fcc::stft_transforms_per_block(N);
+    for (int a = 0; a < num_arrays; ++a) {
+      fcc::BatchArray& d = b->arrays[a];
+      if (d.N != N) continue;
+      d.stft_first = b->stft_items;
+      const int64_t items = (d.T * d.M + fpb - 1) / fpb;
+      b->item_array.insert(b->item_array.end(), size_t(items), int32_t(a));
+      b->stft_items += items;
+    }
+    g.count = b->stft_items - g.first;
+    b->stft_ranges.push_back(g);
   }
   for (auto& kv : by_shape) {
     fcc::BatchClass c;
@@ -676,11 +692,14 @@ fcc_status fcc_batch_create(const fcc_plan* plans, int32_t num_arrays, const int
   b->pair_tuning.assign(b->classes.size(), fcc::PairTuning{});
   b->arrays_off = img;
   b->members_off = batch_align(b->arrays_off + sizeof(fcc::BatchArray) * b->arrays.size());
-  b->image.assign(batch_align(b->members_off + sizeof(int32_t) * b->members.size()), 0);
+  b->items_off = batch_align(b->members_off + sizeof(int32_t) * b->members.size());
+  b->image.assign(batch_align(b->items_off + sizeof(int32_t) * b->item_array.size()), 0);
   for (int a = 0; a < num_arrays; ++a)
     std::memcpy(b->image.data() + b->arrays[a].img_off, b->plans[a].image.data(), b->plans[a].image.size());
   std::memcpy(b->image.data() + b->arrays_off, b->arrays.data(), sizeof(fcc::BatchArray) * b->arrays.size());
   std::memcpy(b->image.data() + b->members_off, b->members.data(), sizeof(int32_t) * b->members.size());
+  if (!b->item_array.empty())
+    std::memcpy(b->image.data() + b->items_off, b->item_array.data(), sizeof(int32_t) * b->item_array.size());
   b->spec_bytes = spec;
   b->queue_off = batch_align(spec);
   b->workspace_bytes = b->queue_off + 256;
@@ -786,20 +805,9 @@ fcc_status fcc_batch_tune(fcc_batch b, const void* d_image, const float* d_audio
   };
   fcc_status result = FCC_OK;
   float best = 3.4e38f;
-  fcc::StftTuning best_s = b->stft_tuning;
-  for (int chunk : {1, 2, 4, 8, 16})
-    for (int bpc : {2, 3, 4}) {
-      const fcc::StftTuning t{chunk, bpc};
-      const float ms = time_of([&] { return fcc::launch_batch_stft(r, t); });
-      if (ms < best) {
-        best = ms;
-        best_s = t;
-      }
-    }
-  if (best >= 3.4e38f) result = set_error(FCC_ERR_HIP, "no front-end tiling ran");
-  b->stft_tuning = best_s;
-  // the pair stage reads the spectra of the chosen front end
-  if (result == FCC_OK && time_of([&] { return fcc::launch_batch_stft(r, b->stft_tuning); }) >= 3.4e38f)
+  // the front end has no shape to choose (one workgroup per block of
+  // transforms); the pair stage reads the spectra it writes
+  if (time_of([&] { return fcc::launch_batch_stft(r); }) >= 3.4e38f)
     result = set_error(FCC_ERR_HIP, "front end failed");
   for (size_t c = 0; c < b->classes.size() && result == FCC_OK; ++c) {
     best = 3.4e38f;
@@ -826,8 +834,8 @@ fcc_status fcc_batch_tuning(fcc_batch b, int32_t* values, int32_t capacity) {
   if (!b || !values) return set_error(FCC_ERR_INVALID_ARG, "NULL argument");
   const int32_t need = 2 + 3 * int32_t(b->classes.size());
   if (capacity < need) return set_error(FCC_ERR_INVALID_ARG, "capacity below 2 + 3 * num_classes");
-  values[0] = b->stft_tuning.chunk;
-  values[1] = b->stft_tuning.blocks_per_cu;
+  values[0] = int32_t(b->stft_ranges.size());
+  values[1] = 0;
   for (size_t c = 0; c < b->classes.size(); ++c) {
     values[2 + 3 * c] = b->pair_tuning[c].ft;
     values[3 + 3 * c] = b->pair_tuning[c].waves;

@@ -46,10 +46,12 @@ struct BatchClass {
   int64_t items(int ft) const;
 };
 
-struct StftTuning {
-  int chunk = 4;             // consecutive items per queue grab
-  int blocks_per_cu = 3;
+// Front-end items of one frame size: items first .. first + count - 1.
+struct BatchStftRange {
+  int N;
+  int64_t first, count;
 };
+
 struct PairTuning {
   int ft = 16;               // frames per item
   int waves = 4;             // wavefronts per workgroup
@@ -64,14 +66,14 @@ struct BatchRun {
   const float* audio;
   unsigned char* spec;
   int32_t* tdoa;
-  int* queue;                // device counters: [0] front end, [1 + c] class c
-  int64_t stft_items;
-  std::vector<int> sizes;    // frame sizes present
+  int* queue;                // device counters: [1 + c] class c
+  const int32_t* item_array; // device: array of every front-end item
+  std::vector<BatchStftRange> stft_ranges;   // one per frame size present
   fcc_precision precision;
   hipStream_t stream;
 };
 
-hipError_t launch_batch_stft(const BatchRun& r, const StftTuning& t);
+hipError_t launch_batch_stft(const BatchRun& r);
 hipError_t launch_batch_pair(const BatchRun& r, const BatchClass& c, const PairTuning& t);
 int stft_transforms_per_block(int N);
 int batch_head_words(int Dpad, int NH, int TT, int P);   // LDS words before the wavefront slabs
