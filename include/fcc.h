@@ -250,10 +250,11 @@ fcc_status fcc_doa(fcc_plan plan, const float* d_y, int64_t num_frames, const fl
  * rank (each with its own plan) in one pass: the front end of every array in
  * one launch per frame size present (one workgroup per block of transforms),
  * and the pair stage of every array in one persistent launch per class of
- * arrays sharing a matrix-core tile shape, with work items (array, tile of
- * frames) taken from a queue.  With use_graph the pass is captured once into a
- * graph (per set of buffer pointers) and replayed.  fcc_batch_tune times
- * candidate pair-stage tile shapes on the given buffers and keeps the fastest.
+ * arrays sharing a matrix-core tile shape, each workgroup taking one
+ * contiguous run of the class's frames.  With use_graph the pass is captured
+ * once into a graph (per set of buffer pointers) and replayed.
+ * fcc_batch_tune times candidate pair-stage launch shapes on the given buffers
+ * and keeps the fastest.
  * Limits: every plan FP16 or BF16 storage (the same), method FCC, alpha = 1,
  * M <= 16, N >= 32, I <= 48, rank <= 32 (FCC_ERR_UNSUPPORTED otherwise).
  * Plans are copied; num_samples[a] fixes array a's length L_a at creation.
@@ -287,8 +288,9 @@ fcc_status fcc_batch_tdoa(fcc_batch batch, const void* d_image, const float* d_a
 fcc_status fcc_batch_tune(fcc_batch batch, const void* d_image, const float* d_audio, int32_t* d_tdoa,
                           void* d_workspace, hipStream_t stream);
 /* The launch shapes in use: values[0] the number of front-end launches (frame
- * sizes present), values[1] 0, then per class (frames per item, wavefronts
- * per workgroup, workgroups per compute unit); capacity >= 2 + 3 num_classes. */
+ * sizes present), values[1] 0, then per class (workgroups launched, wavefronts
+ * per workgroup, workgroups per compute unit asked for); capacity >=
+ * 2 + 3 num_classes. */
 fcc_status fcc_batch_tuning(fcc_batch batch, int32_t* values, int32_t capacity);
 
 /* ---- learned sub-sample TDoA ------------------------------------------------

@@ -103,7 +103,7 @@ class Batch:
         _lib.check(self._lib.fcc_batch_tuning(self._h, v, cap))
         v = list(v)
         return {"front_end": {"launches": v[0]},
-                "pair_classes": [{"frames_per_item": v[2 + 3 * c], "waves": v[3 + 3 * c],
+                "pair_classes": [{"workgroups": v[2 + 3 * c], "waves": v[3 + 3 * c],
                                   "blocks_per_cu": v[4 + 3 * c]} for c in range(self.info.num_classes)]}
 
     def split(self, tdoa):

@@ -6,11 +6,11 @@
 //     numbered consecutively and a host-built table maps each to its array;
 //   - pair stage: one persistent launch per class of arrays that share the
 //     matrix-core tile shape (components in blocks of four, lags in tiles of
-//     16); an item is a tile of consecutive frames of one array, taken from
-//     an atomic queue; each workgroup stages the class's item prefix in LDS
-//     once, and the array's tables when the array changes.
-// The queues are counters in the workspace, cleared by a fill kernel, so the
-// whole sequence can be captured in one graph.
+//     16); each workgroup takes one contiguous run of the class's frames,
+//     split by an estimated per-frame cost, and stages an array's tables
+//     where its run enters that array.
+// Nothing is counted at run time, so the whole sequence can be captured in
+// one graph.
 #include "kernels.hpp"
 #include "pair_mfma_core.hpp"
 #include "stft_core.hpp"
@@ -43,100 +43,75 @@ __global__ __launch_bounds__(stft_core::kThreads) void batch_stft_kernel(
                                      reinterpret_cast<typename S::T*>(spec_base + d.spec_off), it - d.stft_first);
 }
 
-// Tiles of ft frames of member c start at item first[c]; first[n] is the
-// class's item count.  Computed once per workgroup by wavefront 0: each lane
-// sums a run of members, a 64-lane scan gives the runs' offsets.
-__device__ __forceinline__ void tile_prefix(const BatchArray* __restrict__ arrays, const int32_t* __restrict__ members,
-                                            int n, int ft, int* __restrict__ first) {
-  if (threadIdx.x >= 64) return;
-  const int lane = threadIdx.x, run = (n + 63) / 64, c0 = lane * run, c1 = c0 + run < n ? c0 + run : n;
-  int sum = 0;
-  for (int c = c0; c < c1; ++c) sum += (int)((arrays[members[c]].T + ft - 1) / ft);
-  int incl = sum;
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const int v = __shfl_up(incl, off, 64);
-    if (lane >= off) incl += v;
-  }
-  int at = incl - sum;                           // items before this lane's run
-  for (int c = c0; c < c1; ++c) {
-    first[c] = at;
-    at += (int)((arrays[members[c]].T + ft - 1) / ft);
-  }
-  if (lane == 63) first[n] = incl;
-}
-
+// Pair stage of one class: workgroup b takes the frames whose start lies in
+// [W b / B, W (b + 1) / B) of the class's cost scale, where member c's frames
+// weigh w_c each and start at wprefix[c] (W = wprefix[n]).  The runs are
+// contiguous, so a workgroup stages an array's tables only where its run
+// crosses into the next array and its wavefronts keep their next-frame
+// prefetch going across the run, as in the single-array kernel.
 template <class S, int KB, int TT, int kWaves>
 __global__ __launch_bounds__(64 * kWaves, 2) void batch_pair_kernel(
-    const BatchArray* __restrict__ arrays, const int32_t* __restrict__ members, int n_members, int ft,
-    const unsigned char* __restrict__ image, const unsigned char* __restrict__ spec_base,
-    int32_t* __restrict__ tdoa_base, int* __restrict__ queue, int slab_words, int prefix_off) {
+    const BatchArray* __restrict__ arrays, const int32_t* __restrict__ members, int n_members,
+    const int64_t* __restrict__ wprefix, const unsigned char* __restrict__ image,
+    const unsigned char* __restrict__ spec_base, int32_t* __restrict__ tdoa_base, int slab_words) {
   extern __shared__ uint32_t lds_all[];
-  __shared__ int item_sh[3];
+  __shared__ long long run_sh[3];
   const int wave = threadIdx.x >> 6;
-  // the item prefix lives past the largest table head and the slabs; prefix_off < 0: the class is
-  // too large to stage it and thread 0 walks the member list instead
-  const bool staged = prefix_off >= 0;
-  int* first = reinterpret_cast<int*>(lds_all + (staged ? prefix_off : 0));
-  if (staged) {
-    tile_prefix(arrays, members, n_members, ft, first);
-    __syncthreads();
+  // thread 0 alone walks the runs: the member it is at and the cost range
+  int c = 0;
+  int64_t w0 = 0, w1 = 0;
+  if (threadIdx.x == 0) {
+    const int64_t W = wprefix[n_members];
+    w0 = W * (int64_t)blockIdx.x / gridDim.x;
+    w1 = W * ((int64_t)blockIdx.x + 1) / gridDim.x;
+    int lo = 0, hi = n_members - 1;               // last member starting at or before w0
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (wprefix[mid] <= w0) lo = mid;
+      else hi = mid - 1;
+    }
+    c = lo;
   }
-  int cur = -1;
   for (;;) {
     if (threadIdx.x == 0) {
-      int rem = atomicAdd(queue, 1), a = -1, t0 = 0, t1 = 0;
-      if (staged) {
-        // item -> member: last c with first[c] <= rem
-        if (rem < first[n_members]) {
-          int lo = 0, hi = n_members - 1;
-          while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (first[mid] <= rem) lo = mid;
-            else hi = mid - 1;
-          }
-          a = members[lo];
-          const int64_t T = arrays[a].T;
-          t0 = (rem - first[lo]) * ft;
-          t1 = (int)(t0 + ft < T ? t0 + ft : T);
-        }
-      } else {
-        // walk the class's arrays
-        for (int c = 0; c < n_members; ++c) {
-          const int m = members[c];
-          const int64_t T = arrays[m].T;
-          const int tiles = (int)((T + ft - 1) / ft);
-          if (rem < tiles) {
-            a = m;
-            t0 = rem * ft;
-            t1 = (int)(t0 + ft < T ? t0 + ft : T);
-            break;
-          }
-          rem -= tiles;
+      long long a = -1, tb = 0, te = 0;
+      for (; c < n_members && wprefix[c] < w1; ++c) {
+        const int m = members[c];
+        const int64_t T = arrays[m].T;
+        if (T <= 0) continue;
+        const int64_t pre = wprefix[c], w = (wprefix[c + 1] - pre) / T;
+        // frame t starts at pre + t w; this run keeps the starts in [w0, w1)
+        const int64_t b0 = w0 > pre ? (w0 - pre + w - 1) / w : 0;
+        int64_t b1 = (w1 - pre + w - 1) / w;
+        if (b1 > T) b1 = T;
+        if (b0 < b1) {
+          a = m;
+          tb = b0;
+          te = b1;
+          ++c;
+          break;
         }
       }
-      item_sh[0] = a;
-      item_sh[1] = t0;
-      item_sh[2] = t1;
+      run_sh[0] = a;
+      run_sh[1] = tb;
+      run_sh[2] = te;
     }
     __syncthreads();
-    const int a = item_sh[0], t0 = item_sh[1], t1 = item_sh[2];
-    __syncthreads();                                   // read before thread 0 takes the next item
+    const int a = (int)run_sh[0];
+    const int64_t tb = run_sh[1], te = run_sh[2];
+    __syncthreads();                                   // read before thread 0 writes the next run
     if (a < 0) break;                                  // the same for every thread of the block
     const BatchArray& d = arrays[a];
     const int NH = d.N / 2;
-    if (a != cur) {
-      pair_core::stage_tables<KB, TT>(lds_all, NH, d.P,
-                                      reinterpret_cast<const uint32_t*>(image + d.img_off + d.tab_prow16),
-                                      reinterpret_cast<const float*>(image + d.img_off + d.tab_gexp),
-                                      image + d.img_off + d.tab_pairs, 64 * kWaves);
-      __syncthreads();
-      cur = a;
-    }
+    pair_core::stage_tables<KB, TT>(lds_all, NH, d.P,
+                                    reinterpret_cast<const uint32_t*>(image + d.img_off + d.tab_prow16),
+                                    reinterpret_cast<const float*>(image + d.img_off + d.tab_gexp),
+                                    image + d.img_off + d.tab_pairs, 64 * kWaves);
+    __syncthreads();
     uint32_t* slab = lds_all + pair_core::head_words(4 * KB, NH, TT, d.P) + wave * slab_words;
     pair_core::run_frames<S, KB, TT, false>(lds_all, slab,
                                             reinterpret_cast<const typename S::T*>(spec_base + d.spec_off), d.M,
-                                            d.P, NH, d.I, d.lag0, (int64_t)t0 + wave, t1, kWaves,
+                                            d.P, NH, d.I, d.lag0, tb + wave, te, kWaves,
                                             tdoa_base + d.tdoa_off, nullptr);
     __syncthreads();                                   // every wave is done before the tables change
   }
@@ -152,36 +127,28 @@ int num_cus() {
 }
 
 template <class S, int KB, int TT, int WV>
-hipError_t launch_pair_class(const BatchRun& r, const BatchClass& c, int ft, int blocks_per_cu) {
-  if (ft < 1 || blocks_per_cu < 1) return hipErrorInvalidValue;
+hipError_t launch_pair_class(const BatchRun& r, const BatchClass& c, int blocks_per_cu) {
+  if (blocks_per_cu < 1) return hipErrorInvalidValue;
   auto k = batch_pair_kernel<S, KB, TT, WV>;
-  const size_t base_words = size_t(c.head_words_max) + size_t(WV) * c.slab_words_max;
-  if (sizeof(uint32_t) * base_words > 160 * 1024) return hipErrorInvalidValue;
-  // stage the class's item prefix when it fits beside the tables and slabs
-  const size_t prefix_words = size_t(c.member_count) + 1;
-  const bool staged = sizeof(uint32_t) * (base_words + prefix_words) <= 160 * 1024;
-  const size_t lds = sizeof(uint32_t) * (base_words + (staged ? prefix_words : 0));
+  const size_t lds = sizeof(uint32_t) * (size_t(c.head_words_max) + size_t(WV) * c.slab_words_max);
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  const int64_t items = c.items(ft);
-  int64_t blocks = (int64_t)num_cus() * blocks_per_cu * (4 / WV);
-  if (blocks > items) blocks = items;
+  const int64_t blocks = c.workgroups(num_cus(), blocks_per_cu, WV);
   if (blocks < 1) return hipSuccess;
   hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * WV), lds, r.stream, r.arrays, r.members + c.member_first,
-                     c.member_count, ft, r.image, r.spec, r.tdoa, r.queue + 1 + c.index, c.slab_words_max,
-                     staged ? int(base_words) : -1);
+                     c.member_count, reinterpret_cast<const int64_t*>(r.image + c.wprefix_off), r.image, r.spec,
+                     r.tdoa, c.slab_words_max);
   return hipGetLastError();
 }
 
 template <class S, int KB, int TT>
 hipError_t launch_pair_waves(const BatchRun& r, const BatchClass& c, const PairTuning& t) {
-  // four wavefronts per workgroup when their slabs fit in LDS, else two
-  const size_t lds4 = sizeof(uint32_t) * (size_t(c.head_words_max) + 4 * size_t(c.slab_words_max));
-  if (t.waves == 4 && lds4 <= 160 * 1024) return launch_pair_class<S, KB, TT, 4>(r, c, t.ft, t.blocks_per_cu);
-  return launch_pair_class<S, KB, TT, 2>(r, c, t.ft, t.blocks_per_cu);
+  if (batch_pair_waves(c, t) == 4) return launch_pair_class<S, KB, TT, 4>(r, c, t.blocks_per_cu);
+  return launch_pair_class<S, KB, TT, 2>(r, c, t.blocks_per_cu);
 }
 
 template <class S, int KB>
@@ -230,11 +197,27 @@ int stft_transforms_per_block(int N) {
   return 0;
 }
 
-int64_t BatchClass::items(int ft) const {
-  int64_t n = 0;
-  for (int64_t T : member_frames) n += (T + ft - 1) / ft;
-  return n;
+// four wavefronts per workgroup when asked for and their slabs fit in LDS, else two
+int batch_pair_waves(const BatchClass& c, const PairTuning& t) {
+  const size_t lds4 = sizeof(uint32_t) * (size_t(c.head_words_max) + 4 * size_t(c.slab_words_max));
+  return t.waves == 4 && lds4 <= 160 * 1024 ? 4 : 2;
 }
+
+int64_t batch_pair_workgroups(const BatchClass& c, const PairTuning& t) {
+  return c.workgroups(num_cus(), t.blocks_per_cu, batch_pair_waves(c, t));
+}
+
+// workgroups of one class launch: persistent, at most one per frame
+int64_t BatchClass::workgroups(int cus, int blocks_per_cu, int waves) const {
+  int64_t frames = 0;
+  for (int64_t T : member_frames) frames += T;
+  int64_t blocks = int64_t(cus) * blocks_per_cu * (4 / waves);
+  return blocks < frames ? blocks : frames;
+}
+
+// cost of one frame on the class's cost scale: K steps of the projection plus
+// a fixed share for staging, expansion and the argmax
+int64_t pair_frame_weight(int N) { return N / 32 + 4; }
 
 namespace {
 

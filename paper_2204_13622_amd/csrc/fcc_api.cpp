@@ -5,6 +5,7 @@
 #include <cstdint>
 #include <cstring>
 #include <algorithm>
+#include <tuple>
 #include <map>
 #include <new>
 #include <string>
@@ -28,7 +29,7 @@ struct fcc_batch_s {
   std::vector<unsigned char> image;
   size_t arrays_off = 0, members_off = 0, items_off = 0;
   int64_t audio_floats = 0, tdoa_count = 0, stft_items = 0;
-  size_t spec_bytes = 0, queue_off = 0, workspace_bytes = 0;
+  size_t spec_bytes = 0, workspace_bytes = 0;
   std::vector<fcc::BatchStftRange> stft_ranges;   // front-end items, grouped by frame size
   std::vector<int32_t> item_array;                // array of every front-end item
   fcc_precision precision = FCC_FP16;
@@ -575,7 +576,6 @@ fcc::BatchRun batch_run(fcc_batch b, const void* d_image, const float* d_audio, 
   r.audio = d_audio;
   r.spec = static_cast<unsigned char*>(d_ws);
   r.tdoa = d_tdoa;
-  r.queue = reinterpret_cast<int*>(static_cast<unsigned char*>(d_ws) + b->queue_off);
   r.item_array = reinterpret_cast<const int32_t*>(img + b->items_off);
   r.stft_ranges = b->stft_ranges;
   r.precision = b->precision;
@@ -584,9 +584,8 @@ fcc::BatchRun batch_run(fcc_batch b, const void* d_image, const float* d_audio, 
 }
 
 hipError_t batch_enqueue(fcc_batch b, const fcc::BatchRun& r) {
-  hipError_t e = fcc::launch_fill_zero(reinterpret_cast<float*>(r.queue), int64_t(1 + b->classes.size()), r.stream);
+  hipError_t e = fcc::launch_batch_stft(r);
   if (e != hipSuccess) return e;
-  if ((e = fcc::launch_batch_stft(r)) != hipSuccess) return e;
   for (size_t c = 0; c < b->classes.size(); ++c)
     if ((e = fcc::launch_batch_pair(r, b->classes[c], b->pair_tuning[c])) != hipSuccess) return e;
   return hipSuccess;
@@ -614,7 +613,9 @@ fcc_status fcc_batch_create(const fcc_plan* plans, int32_t num_arrays, const int
     return set_error(st, msg);
   };
   b->precision = plans[0] ? plans[0]->p.precision : FCC_FP16;
-  std::map<std::pair<int, int>, std::vector<int>> by_shape;
+  // classes: arrays sharing the tile shape (components in blocks of four, lag
+  // tiles) and the frame size, so a class's LDS is sized for its own frames
+  std::map<std::tuple<int, int, int>, std::vector<int>> by_shape;
   size_t img = 0, spec = 0;
   for (int a = 0; a < num_arrays; ++a) {
     if (!plans[a]) return fail(FCC_ERR_INVALID_ARG, "NULL plan");
@@ -651,7 +652,7 @@ fcc_status fcc_batch_create(const fcc_plan* plans, int32_t num_arrays, const int
     spec += batch_align(size_t(d.T) * p.M * (p.N / 2) * p.spec_elem);
     img += batch_align(p.layout.total);
     b->arrays.push_back(d);
-    by_shape[{kb, tt}].push_back(a);
+    by_shape[{kb, tt, p.N}].push_back(a);
   }
   // front-end items: blocks of transforms, numbered frame size by frame size
   // (one launch per size), array by array within a size
@@ -673,37 +674,46 @@ fcc_status fcc_batch_create(const fcc_plan* plans, int32_t num_arrays, const int
     g.count = b->stft_items - g.first;
     b->stft_ranges.push_back(g);
   }
+  std::vector<std::vector<int64_t>> prefixes;     // per class: cost prefix over its members
   for (auto& kv : by_shape) {
+    std::vector<int64_t> c_prefix(1, 0);
     fcc::BatchClass c;
     c.index = int(b->classes.size());
-    c.kb = kv.first.first;
-    c.tt = kv.first.second;
+    c.kb = std::get<0>(kv.first);
+    c.tt = std::get<1>(kv.first);
     c.member_first = int(b->members.size());
     c.member_count = int(kv.second.size());
     for (int a : kv.second) {
       const fcc::BatchArray& d = b->arrays[a];
       b->members.push_back(a);
       c.member_frames.push_back(d.T);
+      c_prefix.push_back(c_prefix.back() + d.T * fcc::pair_frame_weight(d.N));
       c.head_words_max = std::max(c.head_words_max, fcc::batch_head_words(4 * c.kb, d.N / 2, c.tt, d.P));
       c.slab_words_max = std::max(c.slab_words_max, fcc::batch_slab_words(d.N, d.I));
     }
     b->classes.push_back(c);
+    prefixes.push_back(std::move(c_prefix));
   }
   b->pair_tuning.assign(b->classes.size(), fcc::PairTuning{});
   b->arrays_off = img;
   b->members_off = batch_align(b->arrays_off + sizeof(fcc::BatchArray) * b->arrays.size());
   b->items_off = batch_align(b->members_off + sizeof(int32_t) * b->members.size());
-  b->image.assign(batch_align(b->items_off + sizeof(int32_t) * b->item_array.size()), 0);
+  size_t end = batch_align(b->items_off + sizeof(int32_t) * b->item_array.size());
+  for (size_t c = 0; c < b->classes.size(); ++c) {
+    b->classes[c].wprefix_off = end;
+    end = batch_align(end + sizeof(int64_t) * prefixes[c].size());
+  }
+  b->image.assign(end, 0);
   for (int a = 0; a < num_arrays; ++a)
     std::memcpy(b->image.data() + b->arrays[a].img_off, b->plans[a].image.data(), b->plans[a].image.size());
   std::memcpy(b->image.data() + b->arrays_off, b->arrays.data(), sizeof(fcc::BatchArray) * b->arrays.size());
   std::memcpy(b->image.data() + b->members_off, b->members.data(), sizeof(int32_t) * b->members.size());
   if (!b->item_array.empty())
     std::memcpy(b->image.data() + b->items_off, b->item_array.data(), sizeof(int32_t) * b->item_array.size());
+  for (size_t c = 0; c < b->classes.size(); ++c)
+    std::memcpy(b->image.data() + b->classes[c].wprefix_off, prefixes[c].data(), sizeof(int64_t) * prefixes[c].size());
   b->spec_bytes = spec;
-  b->queue_off = batch_align(spec);
-  b->workspace_bytes = b->queue_off + 256;
-  if (b->classes.size() + 1 > 64) return fail(FCC_ERR_UNSUPPORTED, "too many tile classes in one batch");
+  b->workspace_bytes = batch_align(spec) + 256;
   *out = b;
   return FCC_OK;
 }
@@ -789,13 +799,12 @@ fcc_status fcc_batch_tune(fcc_batch b, const void* d_image, const float* d_audio
     return set_error(FCC_ERR_HIP, "event creation failed");
   }
   const int reps = 3;
-  // time `launch` (queues cleared first) reps times; +inf when it cannot run
+  // time `launch` reps times after one untimed run; +inf when it cannot run
   auto time_of = [&](auto&& launch) -> float {
     hipError_t e = hipSuccess;
     for (int w = 0; w < 1 + reps && e == hipSuccess; ++w) {
       if (w == 1) hipEventRecord(e0, stream);
-      e = fcc::launch_fill_zero(reinterpret_cast<float*>(r.queue), int64_t(1 + b->classes.size()), stream);
-      if (e == hipSuccess) e = launch();
+      e = launch();
     }
     hipEventRecord(e1, stream);
     if (hipEventSynchronize(e1) != hipSuccess || e != hipSuccess) return 3.4e38f;
@@ -812,16 +821,15 @@ fcc_status fcc_batch_tune(fcc_batch b, const void* d_image, const float* d_audio
   for (size_t c = 0; c < b->classes.size() && result == FCC_OK; ++c) {
     best = 3.4e38f;
     fcc::PairTuning best_p = b->pair_tuning[c];
-    for (int ft : {4, 8, 16, 32, 64})
-      for (int waves : {2, 4})
-        for (int bpc : {1, 2, 3}) {
-          const fcc::PairTuning t{ft, waves, bpc};
-          const float ms = time_of([&] { return fcc::launch_batch_pair(r, b->classes[c], t); });
-          if (ms < best) {
-            best = ms;
-            best_p = t;
-          }
+    for (int waves : {2, 4})
+      for (int bpc : {1, 2, 3, 4}) {
+        const fcc::PairTuning t{waves, bpc};
+        const float ms = time_of([&] { return fcc::launch_batch_pair(r, b->classes[c], t); });
+        if (ms < best) {
+          best = ms;
+          best_p = t;
         }
+      }
     if (best >= 3.4e38f) result = set_error(FCC_ERR_HIP, "no pair tiling ran");
     b->pair_tuning[c] = best_p;
   }
@@ -837,8 +845,8 @@ fcc_status fcc_batch_tuning(fcc_batch b, int32_t* values, int32_t capacity) {
   values[0] = int32_t(b->stft_ranges.size());
   values[1] = 0;
   for (size_t c = 0; c < b->classes.size(); ++c) {
-    values[2 + 3 * c] = b->pair_tuning[c].ft;
-    values[3 + 3 * c] = b->pair_tuning[c].waves;
+    values[2 + 3 * c] = int32_t(fcc::batch_pair_workgroups(b->classes[c], b->pair_tuning[c]));
+    values[3 + 3 * c] = fcc::batch_pair_waves(b->classes[c], b->pair_tuning[c]);
     values[4 + 3 * c] = b->pair_tuning[c].blocks_per_cu;
   }
   return FCC_OK;

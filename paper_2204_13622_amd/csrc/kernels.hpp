@@ -43,8 +43,12 @@ struct BatchClass {
   int member_first = 0, member_count = 0;   // slice of the member list
   std::vector<int64_t> member_frames;
   int head_words_max = 0, slab_words_max = 0;
-  int64_t items(int ft) const;
+  size_t wprefix_off = 0;    // image offset of the cost prefix [member_count + 1] (int64)
+  int64_t workgroups(int cus, int blocks_per_cu, int waves) const;
 };
+
+// cost of one pair-stage frame of frame size N on a class's cost scale
+int64_t pair_frame_weight(int N);
 
 // Front-end items of one frame size: items first .. first + count - 1.
 struct BatchStftRange {
@@ -53,7 +57,6 @@ struct BatchStftRange {
 };
 
 struct PairTuning {
-  int ft = 16;               // frames per item
   int waves = 4;             // wavefronts per workgroup
   int blocks_per_cu = 2;
 };
@@ -66,7 +69,6 @@ struct BatchRun {
   const float* audio;
   unsigned char* spec;
   int32_t* tdoa;
-  int* queue;                // device counters: [1 + c] class c
   const int32_t* item_array; // device: array of every front-end item
   std::vector<BatchStftRange> stft_ranges;   // one per frame size present
   fcc_precision precision;
@@ -75,6 +77,8 @@ struct BatchRun {
 
 hipError_t launch_batch_stft(const BatchRun& r);
 hipError_t launch_batch_pair(const BatchRun& r, const BatchClass& c, const PairTuning& t);
+int batch_pair_waves(const BatchClass& c, const PairTuning& t);          // wavefronts per workgroup in use
+int64_t batch_pair_workgroups(const BatchClass& c, const PairTuning& t); // workgroups of the class's launch
 int stft_transforms_per_block(int N);
 int batch_head_words(int Dpad, int NH, int TT, int P);   // LDS words before the wavefront slabs
 int batch_slab_words(int N, int I);                      // LDS words of one wavefront slab
