@@ -25,6 +25,7 @@
 // The lag rows of every microphone go to LDS, where each pair adds its two
 // halves and takes the first index of the largest value.
 #pragma once
+#include <type_traits>
 #include "device_common.hpp"
 #include "kernels.hpp"
 
@@ -150,6 +151,7 @@ __device__ __forceinline__ void run_frames(const uint32_t* lds_all, uint32_t* sl
 
   const h8 sgn = {-1, 1, -1, 1, -1, 1, -1, 1};
   const int nsteps = NH / 16;
+  const int nib = (M + 3) >> 2;                 // blocks of four microphones holding any microphone
 
   for (; t < T; t += stride) {
     // ---- stage the frame into the slab --------------------------------------
@@ -191,9 +193,11 @@ __device__ __forceinline__ void run_frames(const uint32_t* lds_all, uint32_t* sl
     const uint32_t* own = slab + col * row + 4 * g;
     const uint32_t* amic = slab + (col & 3) * row + 4 * g;
     const uint32_t* prow = ptab + (col >> 2) * prow_words + 4 * g;
-    // one K step: 16 slots (32 interleaved re / im values); every tile of
-    // four microphone blocks runs (rows of absent microphones are zero)
-    auto kstep = [&](int off, bool dc_slot) {
+    // one K step: 16 slots (32 interleaved re / im values).  ALL: every block
+    // of four microphones holds one (all four blocks run, A rows loaded
+    // first); otherwise only the blocks that hold any run (rows of absent
+    // microphones are zero and have nothing to add).
+    auto kstep = [&](auto all, int off, bool dc_slot) {
       const uint4 rw = *reinterpret_cast<const uint4*>(own + off);
       const h8 raw = __builtin_bit_cast(h8, rw);
       // B: the rotated spectrum (a - b, a + b) of microphone `col`; the packed
@@ -204,28 +208,50 @@ __device__ __forceinline__ void run_frames(const uint32_t* lds_all, uint32_t* sl
         B[0] = raw[0];
         B[1] = raw[1];
       }
-      h8 Am[4];
-#pragma unroll
-      for (int ib = 0; ib < 4; ++ib)
-        Am[ib] = __builtin_bit_cast(h8, *reinterpret_cast<const uint4*>(amic + 4 * ib * row + off));
-#pragma unroll
-      for (int kb = 0; kb < KB; ++kb) {
-        const h8 pk = __builtin_bit_cast(h8, *reinterpret_cast<const uint4*>(prow + 4 * kb * prow_words + off));
+      if constexpr (decltype(all)::value) {
+        h8 Am[4];
 #pragma unroll
         for (int ib = 0; ib < 4; ++ib)
-          acc[kb][ib] = __builtin_amdgcn_mfma_f32_16x16x32_f16(Am[ib] * pk, B, acc[kb][ib], 0, 0, 0);
+          Am[ib] = __builtin_bit_cast(h8, *reinterpret_cast<const uint4*>(amic + 4 * ib * row + off));
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb) {
+          const h8 pk = __builtin_bit_cast(h8, *reinterpret_cast<const uint4*>(prow + 4 * kb * prow_words + off));
+#pragma unroll
+          for (int ib = 0; ib < 4; ++ib)
+            acc[kb][ib] = __builtin_amdgcn_mfma_f32_16x16x32_f16(Am[ib] * pk, B, acc[kb][ib], 0, 0, 0);
+        }
+      } else {
+        h8 pk[KB];
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb)
+          pk[kb] = __builtin_bit_cast(h8, *reinterpret_cast<const uint4*>(prow + 4 * kb * prow_words + off));
+#pragma unroll
+        for (int ib = 0; ib < 4; ++ib) {
+          if (ib < nib) {
+            const h8 Am = __builtin_bit_cast(h8, *reinterpret_cast<const uint4*>(amic + 4 * ib * row + off));
+#pragma unroll
+            for (int kb = 0; kb < KB; ++kb)
+              acc[kb][ib] = __builtin_amdgcn_mfma_f32_16x16x32_f16(Am * pk[kb], B, acc[kb][ib], 0, 0, 0);
+          }
+        }
       }
     };
-    if (KB <= 3 && nsteps >= 2) {               // two K steps per trip (nsteps = N/32 is a power of two);
-                                                // wider bases have no registers to spare for it
-      for (int s = 0; s < nsteps; s += 2) {
-        kstep(16 * s, s == 0 && g == 0);
-        kstep(16 * s + 16, false);
+    auto project = [&](auto all) {
+      if (KB <= 3 && KB * TT <= 6 && nsteps >= 2) {   // two K steps per trip (nsteps = N/32 is a power
+                                                      // of two); wider tiles have no registers to spare
+        for (int s = 0; s < nsteps; s += 2) {
+          kstep(all, 16 * s, s == 0 && g == 0);
+          kstep(all, 16 * s + 16, false);
+        }
+      } else {
+        kstep(all, 0, g == 0);
+        for (int s = 1; s < nsteps; ++s) kstep(all, 16 * s, false);
       }
-    } else {
-      kstep(0, g == 0);
-      for (int s = 1; s < nsteps; ++s) kstep(16 * s, false);
-    }
+    };
+    if (nib == 4)
+      project(std::true_type{});
+    else
+      project(std::false_type{});
     wave_sync();   // every lane has read the spectra; the slab now takes Y
 
     // ---- expansion: Y_i(tau, j) = sum_k G(tau, k) H_k(i, j) --------------------
@@ -237,6 +263,7 @@ __device__ __forceinline__ void run_frames(const uint32_t* lds_all, uint32_t* sl
       for (int kb = 0; kb < KB; ++kb) gx[tt][kb] = gsh[(16 * tt + col) * Dp + 4 * kb + g];
 #pragma unroll
     for (int ib = 0; ib < 4; ++ib) {
+      if (ib >= nib) continue;                  // rows i >= M are never read
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int i = 4 * ib + q;

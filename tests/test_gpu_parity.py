@@ -316,7 +316,9 @@ def _quantized_reference(X, dtype_np, B):
 
 @pytest.mark.parametrize("config,seconds,D,M", [(2, 1.0, 6, None), (2, 1.0, 11, None),
                                                 (3, 0.3, 15, None), (3, 0.3, 29, None),
-                                                (5, 1.0, 5, None), (2, 1.0, 9, 5), (1, 1.0, 9, None)])
+                                                (5, 1.0, 5, None), (2, 1.0, 9, 5), (1, 1.0, 9, None),
+                                                # one, two and three blocks of four microphones
+                                                (2, 1.0, 6, 2), (2, 1.0, 6, 3), (2, 0.5, 9, 8), (2, 0.5, 9, 12)])
 def test_mfma_pair_stage_fp16(torch, fcc, config, seconds, D, M):
     _say(f"matrix-core pair stage fp16 config {config} D={D} M={M}")
     rec = make_recording(config, seconds=seconds, M=M) if M else make_recording(config, seconds=seconds)
