@@ -555,12 +555,14 @@ fcc_status fcc_doa(fcc_plan plan, const float* d_y, int64_t num_frames, const fl
 
 // ---- batches ---------------------------------------------------------------
 
+}  // extern "C": the helpers below are C++
+
 namespace {
 
 size_t batch_align(size_t b) { return (b + 255) & ~size_t(255); }
 
 void batch_drop_graph(fcc_batch b) {
-  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
   b->exec = nullptr;
   for (auto& k : b->graph_key) k = nullptr;
 }
@@ -601,6 +603,8 @@ fcc_status batch_check(fcc_batch b, const void* d_image, const float* d_audio, i
 }
 
 }  // namespace
+
+extern "C" {
 
 fcc_status fcc_batch_create(const fcc_plan* plans, int32_t num_arrays, const int64_t* num_samples, fcc_batch* out) {
   if (!plans || !num_samples || !out || num_arrays < 1)
@@ -721,7 +725,7 @@ fcc_status fcc_batch_create(const fcc_plan* plans, int32_t num_arrays, const int
 void fcc_batch_destroy(fcc_batch b) {
   if (!b) return;
   batch_drop_graph(b);
-  if (b->capture_stream) hipStreamDestroy(b->capture_stream);
+  if (b->capture_stream) (void)hipStreamDestroy(b->capture_stream);
   delete b;
 }
 
@@ -771,12 +775,12 @@ fcc_status fcc_batch_tdoa(fcc_batch b, const void* d_image, const float* d_audio
     const hipError_t le = batch_enqueue(b, batch_run(b, d_image, d_audio, d_tdoa, d_workspace, b->capture_stream));
     e = hipStreamEndCapture(b->capture_stream, &graph);
     if (le != hipSuccess) {
-      if (graph) hipGraphDestroy(graph);
+      if (graph) (void)hipGraphDestroy(graph);
       return hip_status(le, "batch launch during capture");
     }
     if (e != hipSuccess) return hip_status(e, "graph capture end");
     e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
-    hipGraphDestroy(graph);
+    (void)hipGraphDestroy(graph);
     if (e != hipSuccess) {
       b->exec = nullptr;
       return hip_status(e, "graph instantiation");
@@ -795,7 +799,7 @@ fcc_status fcc_batch_tune(fcc_batch b, const void* d_image, const float* d_audio
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return set_error(FCC_ERR_HIP, "event creation failed");
   if (hipEventCreate(&e1) != hipSuccess) {
-    hipEventDestroy(e0);
+    (void)hipEventDestroy(e0);
     return set_error(FCC_ERR_HIP, "event creation failed");
   }
   const int reps = 3;
@@ -803,13 +807,13 @@ fcc_status fcc_batch_tune(fcc_batch b, const void* d_image, const float* d_audio
   auto time_of = [&](auto&& launch) -> float {
     hipError_t e = hipSuccess;
     for (int w = 0; w < 1 + reps && e == hipSuccess; ++w) {
-      if (w == 1) hipEventRecord(e0, stream);
-      e = launch();
+      if (w == 1) e = hipEventRecord(e0, stream);
+      if (e == hipSuccess) e = launch();
     }
-    hipEventRecord(e1, stream);
-    if (hipEventSynchronize(e1) != hipSuccess || e != hipSuccess) return 3.4e38f;
+    if (e == hipSuccess) e = hipEventRecord(e1, stream);
+    if (e != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return 3.4e38f;
     float ms = 0.f;
-    hipEventElapsedTime(&ms, e0, e1);
+    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) return 3.4e38f;
     return ms;
   };
   fcc_status result = FCC_OK;
@@ -833,8 +837,8 @@ fcc_status fcc_batch_tune(fcc_batch b, const void* d_image, const float* d_audio
     if (best >= 3.4e38f) result = set_error(FCC_ERR_HIP, "no pair tiling ran");
     b->pair_tuning[c] = best_p;
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   return result;
 }
 
