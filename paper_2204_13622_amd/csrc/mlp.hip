@@ -270,12 +270,11 @@ hipError_t forward_impl(const float* theta, int K0, int H, const float* x, int64
 // product in FP16, accumulation, bias, GELU and head in FP32.
 
 __device__ __forceinline__ float gelu_fast(float x) {
-  // tanh(u) = 1 - 2 / (1 + exp(2u)): exact at both tails (exp over- and
-  // underflow); the hardware reciprocal (about 1 ulp) stands in for the
+  // (1 + tanh(u)) / 2 = 1 / (1 + exp(-2u)): exact at both tails (exp over- and
+  // underflow); the hardware reciprocal (about 1 ulp) stands in for a
   // correctly rounded division, whose result is rounded to FP16 anyway
   const float u = kGeluC * (x + kGeluA * x * x * x);
-  const float t = 1.f - 2.f * __builtin_amdgcn_rcpf(1.f + __expf(2.f * u));
-  return 0.5f * x * (1.f + t);
+  return x * __builtin_amdgcn_rcpf(1.f + __expf(-2.f * u));
 }
 
 __device__ __forceinline__ void wave_sync() {
