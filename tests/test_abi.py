@@ -247,3 +247,21 @@ def test_batch_validation_and_layout(fcc):
     big = fcc.Plan(circular_array(17, 0.05), 16000.0, precision="fp16")
     hs = (ctypes.c_void_p * 1)(big._h)
     assert lib.fcc_batch_create(hs, 1, (ctypes.c_int64 * 1)(1000), ctypes.byref(h)) == -2
+
+
+def test_batch_classes_split_by_frame_size(fcc):
+    """Pair-stage classes group arrays by tile shape and frame size: two
+    arrays that differ only in N fall in two classes, equal ones in one."""
+    lib = fcc._lib.load()
+    xyz = square_array(0.05)
+    mk = lambda N: fcc.Plan(xyz, 16000.0, frame_size=N, hop=N // 4, rank=4, precision="fp16")  # noqa: E731
+    for sizes, classes in [((512, 512), 1), ((256, 512), 2), ((256, 512, 1024, 512), 3)]:
+        plans = [mk(N) for N in sizes]
+        n = len(plans)
+        h = ctypes.c_void_p()
+        hs = (ctypes.c_void_p * n)(*[p._h for p in plans])
+        assert lib.fcc_batch_create(hs, n, (ctypes.c_int64 * n)(*([4000] * n)), ctypes.byref(h)) == 0
+        info = fcc._lib.FccBatchInfo()
+        assert lib.fcc_batch_query(h, ctypes.byref(info)) == 0
+        assert info.num_classes == classes, sizes
+        lib.fcc_batch_destroy(h)
