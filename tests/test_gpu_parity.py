@@ -195,6 +195,45 @@ def test_full_size_config2_sampled(torch, fcc):
         _check_fp32(t.cpu().numpy()[frames], y.cpu().numpy()[frames], y_ref, p.tau_max)
 
 
+@pytest.fixture(scope="module")
+def rec3():
+    return make_recording(3)                   # 120 s, 16 mics, 48 kHz: T = 22497 frames
+
+
+@pytest.mark.parametrize("precision,D,min_agree,max_err", [
+    ("fp32", 15, 1.0, EPS32), ("fp16", 15, 0.995, 5e-3), ("bf16", 15, 0.98, 3e-2),
+    ("fp8", 15, 0.90, 0.3), ("fp16", 29, 0.995, 5e-3)])
+def test_full_size_config3_sampled(torch, fcc, rec3, precision, D, min_agree, max_err):
+    """The mixed-precision workload at full size (120 s at 48 kHz, N = 1024)
+    in the launch configuration the library uses for it; the FP64 oracle
+    on the unquantised audio checks a sample of frames."""
+    _say(f"fcc_tdoa config 3 full size, {precision}, D={D}, sampled frames")
+    rec = rec3
+    p = _plan(fcc, rec, D, precision=precision)
+    x = _dev(torch, rec.x)
+    t = p.tdoa(x)
+    y = p.correlation(p.spectra(x))
+    torch.cuda.synchronize()
+    T = p.num_frames(rec.L)
+    assert tuple(t.shape) == (T, 120) and T == 22497
+    rng = np.random.default_rng(3000 + D)
+    frames = np.unique(np.concatenate([[0, T - 1], rng.choice(T, 32, replace=False)]))
+    t_ref, y_ref = O.fcc_tdoa(rec.x, rec.N, rec.hop, p.tau_max, D, frames=frames, return_corr=True)
+    t_s, y_s = t.cpu().numpy()[frames], y.cpu().numpy()[frames]
+    del y
+    if precision == "fp32":
+        rep = _check_fp32(t_s, y_s, y_ref, p.tau_max)
+        print(f"[{precision} D={D}] agreement {rep['agreement']:.5f}", flush=True)
+        return
+    e = corr_errors(y_s, y_ref)
+    rep = tdoa_report(t_s, y_ref, p.tau_max, float(e.max()))
+    print(f"[{precision} D={D}] agreement {rep['agreement']:.5f} max rel err {e.max():.3e} "
+          f"mean {e.mean():.3e}", flush=True)
+    assert rep["agreement"] >= min_agree
+    assert e.max() <= max_err
+    assert rep["mismatch_qualified"] == 0
+
+
 # ------------------------------------------------------------- edge cases --
 
 def test_short_and_empty(torch, fcc):
