@@ -143,9 +143,10 @@ def cpu_baseline(rec, tau_max, D, budget_s):
 
 
 def other_paths(torch, fcc, rec, x, dev, args):
-    """Throughput of the extended paths on the same recording: recursive
-    smoothing (alpha = 0.1, FP32, r = 2 grid), the learned sub-sample stage
-    (untrained weights: the cost is the same) and the DoA search."""
+    """Throughput of the extended paths: recursive smoothing (alpha = 0.1,
+    FP32, r = 2 grid), the mixed-precision workload (48 kHz, N = 1024), the
+    learned sub-sample stage (untrained weights: the cost is the same), the
+    DoA search and a batch of 256 arrays."""
     import numpy as np
     from paper_2204_13622_amd import learned
     out = {}
@@ -159,6 +160,24 @@ def other_paths(torch, fcc, rec, x, dev, args):
         f()
     ms = time_loop(torch, f, steps)
     out["smoothed_alpha0.1_r2_fp32_D11"] = {"ms": round(ms, 4), "pair_frames_per_s": round(T * sm.P / (ms * 1e-3))}
+
+    # the mixed-precision workload: 120 s at 48 kHz, N = 1024, hop 256, D = 15
+    from gen import make_recording
+    rec3 = make_recording(3, seed=args.seed + 1000)
+    x3 = torch.from_numpy(rec3.x).to(dev)
+    for prec in ("fp32", "bf16", "fp16", "fp8"):
+        p3 = fcc.Plan(rec3.mic_xyz, rec3.fs, rec3.c, frame_size=rec3.N, hop=rec3.hop, rank=15, precision=prec)
+        T3 = p3.num_frames(rec3.L)
+        ws3 = torch.empty(p3.workspace_bytes(T3), dtype=torch.uint8, device=dev)
+        o3 = torch.empty((T3, p3.P), dtype=torch.int32, device=dev)
+        f = lambda: p3.tdoa(x3, out=o3, workspace=ws3)  # noqa: E731
+        for _ in range(args.warmup):
+            f()
+        ms = time_loop(torch, f, steps)
+        out[f"fcc_48k_N1024_D15_{prec}"] = {"ms": round(ms, 4), "pair_frames_per_s": round(T3 * p3.P / (ms * 1e-3)),
+                                            "pair_frames": T3 * p3.P}
+        del ws3, o3
+    del x3, rec3
 
     lp = fcc.Plan(rec.mic_xyz, rec.fs, rec.c, frame_size=rec.N, hop=rec.hop, rank=11, precision="fp16")
     T = lp.num_frames(rec.L)
