@@ -37,10 +37,10 @@ size_t lds_bytes(const PairArgs& a, int waves) {
   return sizeof(uint32_t) * (size_t(head_words(a.Dpad, a.N / 2, lag_tiles(a), a.P)) + size_t(waves) * slab_words(a));
 }
 
-// wavefronts per block: four when the block's LDS fits, else two
+// wavefronts per block: four when the block's LDS fits, else three, else two
 int block_waves(const PairArgs& a) {
-  if (lds_bytes(a, 4) <= 160 * 1024) return 4;
-  if (lds_bytes(a, 2) <= 160 * 1024) return 2;
+  for (int w : {4, 3, 2})
+    if (lds_bytes(a, w) <= 160 * 1024) return w;
   return 0;
 }
 
@@ -61,7 +61,7 @@ hipError_t launch5(const PairArgs& a) {
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
   }
   const int64_t need = (a.T + WV - 1) / WV;
-  const int64_t cap = int64_t(2) * cus * (4 / WV);
+  const int64_t cap = int64_t(2) * cus * (WV == 2 ? 2 : 1);
   const int64_t blocks = need < cap ? need : cap;
   hipLaunchKernelGGL(k, dim3((unsigned)blocks), dim3(64 * WV), lds, a.stream,
                      static_cast<const typename S::T*>(a.spec), a.T, a.M, a.P, a.N / 2, a.I,
@@ -72,7 +72,11 @@ hipError_t launch5(const PairArgs& a) {
 
 template <class S, int KB, int TT, bool WY>
 hipError_t launch4(const PairArgs& a) {
-  return block_waves(a) == 4 ? launch5<S, KB, TT, WY, 4>(a) : launch5<S, KB, TT, WY, 2>(a);
+  switch (block_waves(a)) {
+    case 4: return launch5<S, KB, TT, WY, 4>(a);
+    case 3: return launch5<S, KB, TT, WY, 3>(a);
+    default: return launch5<S, KB, TT, WY, 2>(a);
+  }
 }
 
 template <class S, int KB>
