@@ -147,8 +147,11 @@ hipError_t launch_pair_class(const BatchRun& r, const BatchClass& c, int blocks_
 
 template <class S, int KB, int TT>
 hipError_t launch_pair_waves(const BatchRun& r, const BatchClass& c, const PairTuning& t) {
-  if (batch_pair_waves(c, t) == 4) return launch_pair_class<S, KB, TT, 4>(r, c, t.blocks_per_cu);
-  return launch_pair_class<S, KB, TT, 2>(r, c, t.blocks_per_cu);
+  switch (batch_pair_waves(c, t)) {
+    case 4: return launch_pair_class<S, KB, TT, 4>(r, c, t.blocks_per_cu);
+    case 3: return launch_pair_class<S, KB, TT, 3>(r, c, t.blocks_per_cu);
+    default: return launch_pair_class<S, KB, TT, 2>(r, c, t.blocks_per_cu);
+  }
 }
 
 template <class S, int KB>
@@ -197,10 +200,11 @@ int stft_transforms_per_block(int N) {
   return 0;
 }
 
-// four wavefronts per workgroup when asked for and their slabs fit in LDS, else two
+// the wavefronts per workgroup asked for (2, 3 or 4), fewer where their slabs do not fit in LDS
 int batch_pair_waves(const BatchClass& c, const PairTuning& t) {
-  const size_t lds4 = sizeof(uint32_t) * (size_t(c.head_words_max) + 4 * size_t(c.slab_words_max));
-  return t.waves == 4 && lds4 <= 160 * 1024 ? 4 : 2;
+  for (int w = t.waves < 4 ? t.waves : 4; w > 2; --w)
+    if (sizeof(uint32_t) * (size_t(c.head_words_max) + size_t(w) * c.slab_words_max) <= 160 * 1024) return w;
+  return 2;
 }
 
 int64_t batch_pair_workgroups(const BatchClass& c, const PairTuning& t) {
@@ -211,7 +215,7 @@ int64_t batch_pair_workgroups(const BatchClass& c, const PairTuning& t) {
 int64_t BatchClass::workgroups(int cus, int blocks_per_cu, int waves) const {
   int64_t frames = 0;
   for (int64_t T : member_frames) frames += T;
-  int64_t blocks = int64_t(cus) * blocks_per_cu * (4 / waves);
+  int64_t blocks = int64_t(cus) * blocks_per_cu * (waves == 2 ? 2 : 1);
   return blocks < frames ? blocks : frames;
 }
 

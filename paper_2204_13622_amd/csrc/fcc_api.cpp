@@ -825,7 +825,7 @@ fcc_status fcc_batch_tune(fcc_batch b, const void* d_image, const float* d_audio
   for (size_t c = 0; c < b->classes.size() && result == FCC_OK; ++c) {
     best = 3.4e38f;
     fcc::PairTuning best_p = b->pair_tuning[c];
-    for (int waves : {2, 4})
+    for (int waves : {2, 3, 4})
       for (int bpc : {1, 2, 3, 4}) {
         const fcc::PairTuning t{waves, bpc};
         const float ms = time_of([&] { return fcc::launch_batch_pair(r, b->classes[c], t); });
