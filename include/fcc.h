@@ -264,7 +264,7 @@ fcc_status fcc_doa(fcc_plan plan, const float* d_y, int64_t num_frames, const fl
  *               L_a) at offset audio_offset[a] (fcc_batch_layout);
  *   d_tdoa      info.tdoa_count int32: array a's [T_a][P_a] lags (units of 1/r
  *               sample) at offset tdoa_offset[a];
- *   d_workspace info.workspace_bytes, 256-byte aligned (spectra and queues).
+ *   d_workspace info.workspace_bytes, 256-byte aligned (the spectra of every array).
  * A batch object is not thread-safe (tuning and the graph cache mutate it);
  * calls that share a workspace must be ordered. */
 typedef struct fcc_batch_s* fcc_batch;

@@ -38,7 +38,7 @@ struct BatchArray {
 
 // Arrays sharing one matrix-core tile shape (host side).
 struct BatchClass {
-  int index = 0;             // queue slot
+  int index = 0;             // position in the batch's class list
   int kb = 0, tt = 0;        // components in blocks of 4, lags in tiles of 16
   int member_first = 0, member_count = 0;   // slice of the member list
   std::vector<int64_t> member_frames;
