@@ -212,6 +212,35 @@ def test_smoothed_streaming_continues_the_recursion(torch, fcc):
         1e-5 * np.abs(whole["state"].cpu().numpy()).max()
 
 
+def test_smoothed_short_calls(torch, fcc):
+    """Calls of 1, 2, 9 and 17 frames (one chunk, two chunks with a shorter
+    tail, three chunks) carrying the state between them reproduce the oracle's
+    single recursion over all frames."""
+    _say("smoothed short calls")
+    M, N, hop = 4, 512, 128
+    x = random_signals(1300, M, N + 59 * hop)
+    p = fcc.Plan(circular_array(M, 0.05), 16000.0, frame_size=N, hop=hop, rank=8, interp=2, alpha=0.2)
+    spec = p.spectra(_dev(torch, x))
+    T = spec.shape[0]
+    assert T == 60
+    state, ys, ts, t0 = None, [], [], 0
+    for n in (1, 1, 2, 9, 17, 5, T - 35):
+        out = p.tdoa_smoothed(spec[t0:t0 + n].contiguous(), state=state, y=True)
+        state = out["state"]
+        ys.append(out["y"].cpu().numpy())
+        ts.append(out["tdoa"].cpu().numpy())
+        t0 += n
+    y, t = np.concatenate(ys), np.concatenate(ts)
+    y_ref = _smoothed_ref(x, N, hop, p.tau_max, 8, 2, 0.2)
+    assert y.shape == y_ref.shape
+    assert corr_errors(y, y_ref).max() <= EPS32
+    rep = tdoa_report(t, y_ref, 2 * p.tau_max, EPS32)
+    assert rep["mismatch_qualified"] == 0 and rep["invalid_elsewhere"] == 0, rep
+    R_last = O.cross_spectrum(O.stft(x, N, hop), 0.2)[-1]
+    st = state.cpu().numpy()
+    assert np.abs(st[..., 0] + 1j * st[..., 1] - R_last).max() <= 1e-4 * np.abs(R_last).max()
+
+
 def test_smoothed_errors(torch, fcc):
     p = fcc.Plan(PAIR_15CM, 16000.0, frame_size=512, hop=256, tau_max=8, rank=8, interp=2, alpha=0.1)
     spec = p.spectra(_dev(torch, _two_mic(1)))
