@@ -258,6 +258,8 @@ fcc_status fcc_doa(fcc_plan plan, const float* d_y, int64_t num_frames, const fl
  * Limits: every plan FP16 or BF16 storage (the same), method FCC, alpha = 1,
  * M <= 16, N >= 32, I <= 48, rank <= 32 (FCC_ERR_UNSUPPORTED otherwise).
  * Plans are copied; num_samples[a] fixes array a's length L_a at creation.
+ * An array shorter than its frame size has no frames (T_a = 0) and no output;
+ * when no array has a frame, fcc_batch_tdoa and fcc_batch_tune do nothing.
  * Buffers (caller-owned, device):
  *   d_image     info.image_bytes, 256-byte aligned, filled by fcc_batch_upload;
  *   d_audio     info.audio_floats FP32: array a's [M_a][L_a] block (row stride

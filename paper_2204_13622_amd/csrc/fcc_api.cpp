@@ -761,6 +761,7 @@ fcc_status fcc_batch_tdoa(fcc_batch b, const void* d_image, const float* d_audio
                           int32_t use_graph, hipStream_t stream) {
   fcc_status st = batch_check(b, d_image, d_audio, d_tdoa, d_workspace);
   if (st != FCC_OK) return st;
+  if (b->tdoa_count == 0) return FCC_OK;          // no array holds a whole frame: nothing to launch
   if (!use_graph)
     return hip_status(batch_enqueue(b, batch_run(b, d_image, d_audio, d_tdoa, d_workspace, stream)), "batch launch");
   const void* key[4] = {d_image, d_audio, d_tdoa, d_workspace};
@@ -794,6 +795,7 @@ fcc_status fcc_batch_tune(fcc_batch b, const void* d_image, const float* d_audio
                           hipStream_t stream) {
   fcc_status st = batch_check(b, d_image, d_audio, d_tdoa, d_workspace);
   if (st != FCC_OK) return st;
+  if (b->tdoa_count == 0) return FCC_OK;          // nothing to time: the default shapes stay
   batch_drop_graph(b);
   const fcc::BatchRun r = batch_run(b, d_image, d_audio, d_tdoa, d_workspace, stream);
   hipEvent_t e0, e1;

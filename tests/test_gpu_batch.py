@@ -82,3 +82,36 @@ def test_batch_against_oracle(torch, fcc):
         y_ref = O.fcc_corr(R, O.fcc_basis(p.N, p.tau_max, p.rank))
         rep = tdoa_report(out[a].cpu().numpy(), y_ref, p.tau_max, 5e-3)
         assert rep["mismatch_qualified"] == 0 and rep["invalid_elsewhere"] == 0, rep
+
+
+def test_batch_short_and_empty_arrays(torch, fcc):
+    """Arrays with no frame (shorter than the frame size, or no samples), one
+    frame and two frames beside whole ones: the whole arrays equal the
+    single-array path and the empty ones have no output.  A batch in which no
+    array has a frame runs and tunes as a no-op."""
+    _say("batch with short and empty arrays")
+    arrays = batch_arrays(4300, 6, 0.25)
+    plans = _plans(fcc, arrays, "fp16")
+    N = [a["N"] for a in arrays]
+    hop = [a["hop"] for a in arrays]
+    lengths = [N[0] - 1, N[1], N[2] + hop[2], 0, arrays[4]["x"].shape[1], arrays[5]["x"].shape[1]]
+    xs = [np.ascontiguousarray(a["x"][:, :L]) for a, L in zip(arrays, lengths)]
+    b = fcc.Batch(plans, lengths)
+    assert b.frames[:4] == [0, 1, 2, 0]
+    audio = b.pack([torch.from_numpy(x) for x in xs])
+    for graph in (False, True, True):
+        out = [t.cpu().numpy().copy() for t in b.split(b.tdoa(audio, graph=graph))]
+        for a, (p, x) in enumerate(zip(plans, xs)):
+            if b.frames[a] == 0:
+                assert out[a].shape == (0, p.P), a
+            else:
+                assert np.array_equal(out[a], p.tdoa(torch.from_numpy(x).cuda()).cpu().numpy()), (graph, a)
+    empty = fcc.Batch(plans[:2], [N[0] - 1, 5])
+    assert empty.info.tdoa_count == 0
+    audio = empty.pack([torch.from_numpy(np.ascontiguousarray(arrays[0]["x"][:, :N[0] - 1])),
+                        torch.from_numpy(np.ascontiguousarray(arrays[1]["x"][:, :5]))])
+    for graph in (False, True):
+        parts = empty.split(empty.tdoa(audio, graph=graph))
+        assert [tuple(t.shape) for t in parts] == [(0, plans[0].P), (0, plans[1].P)]
+    assert len(empty.tune(audio)["pair_classes"]) == empty.info.num_classes
+    torch.cuda.synchronize()
