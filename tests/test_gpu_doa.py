@@ -60,7 +60,9 @@ def _check_scores(doa, score, y, q):
 
 
 @pytest.mark.parametrize("G,M,r,seconds", [(512, 6, 2, 0.5), (1000, 6, 1, 0.37), (200, 16, 1, 0.3),
-                                           (77, 31, 2, 0.2)])
+                                           (77, 31, 2, 0.2),
+                                           (1, 6, 1, 0.2),         # one direction: always index 0
+                                           (2600, 6, 2, 0.21)])    # eleven lane rounds, the last partial
 def test_doa_scores_match_oracle(torch, fcc, G, M, r, seconds):
     _say(f"DoA parity G={G} M={M} r={r}")
     xyz = _xyz3d(M)
