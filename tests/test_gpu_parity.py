@@ -376,3 +376,36 @@ def test_mfma_pair_stage_fp16(torch, fcc, config, seconds, D, M):
     rep = tdoa_report(t, y_ref, p.tau_max, 5e-3)
     assert rep["mismatch_qualified"] == 0, rep
     assert rep["invalid_elsewhere"] == 0, rep
+
+
+# ------------------------------------------------------- rank and size limits --
+
+@pytest.mark.parametrize("M,N,tau_max,D,precision", [
+    (3, 512, 48, 64, "fp32"),     # largest rank: the fold kernel with 64 components, I = 97
+    (4, 1024, 20, 32, "fp16"),    # largest matrix-core rank: eight blocks of four, three lag tiles
+    (20, 512, 20, 16, "fp16"),    # more than 16 microphones: the direct form
+    (4, 512, 24, 40, "fp16"),     # rank above 32 and I = 49: the direct form
+    (32, 512, 20, 24, "fp16"),    # 32 microphones: 496 pairs over 256 threads, 78 KB of LDS
+])
+def test_rank_and_size_limits(torch, fcc, M, N, tau_max, D, precision):
+    _say(f"limits M={M} N={N} tau_max={tau_max} D={D} {precision}")
+    hop = N // 4
+    x = random_signals(1400 + M + D, M, N + 40 * hop)
+    p = fcc.Plan(circular_array(M, 0.05), 16000.0, frame_size=N, hop=hop, tau_max=tau_max, rank=D,
+                 precision=precision)
+    X = O.stft(x, N, hop)
+    B = O.fcc_basis(N, tau_max, D)
+    if precision == "fp32":
+        spec = _oracle_spec_tensor(torch, X, torch.float32)
+        y_ref, tol = O.fcc_corr(O.phat(O.cross_spectrum(X)), B), EPS32
+    else:
+        packed, y_ref = _quantized_reference(X, np.float16, B)
+        spec, tol = torch.from_numpy(packed.astype(np.float16)).cuda().contiguous(), 5e-3
+    y = p.correlation(spec).cpu().numpy()
+    t = p.tdoa_from_spectra(spec).cpu().numpy()
+    assert y.shape == y_ref.shape == (41, p.P, 2 * tau_max + 1)
+    e = corr_errors(y, y_ref)
+    print(f"max rel corr err {e.max():.3e}", flush=True)
+    assert e.max() <= tol
+    rep = tdoa_report(t, y_ref, tau_max, tol)
+    assert rep["mismatch_qualified"] == 0 and rep["invalid_elsewhere"] == 0, rep
