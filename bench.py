@@ -319,6 +319,22 @@ def main():
             sweep.append({"method": method, "precision": prec, "rank": pl.rank,
                           "ms": round(msq, 4), "pair_frames_per_s": round(Tq * pl.P / (msq * 1e-3))})
         extras = other_paths(torch, fcc, rec, x, dev, args)
+        # context only, never `value`: the same step with the audio handed over
+        # from pinned host memory and the lags returned to it across PCIe
+        xh = torch.empty(tuple(x.shape), dtype=torch.float32, pin_memory=True)
+        xh.copy_(torch.from_numpy(rec.x))
+        oh = torch.empty((T, P), dtype=torch.int32, pin_memory=True)
+
+        def pcie_step():
+            x.copy_(xh, non_blocking=True)
+            step()
+            oh.copy_(out, non_blocking=True)
+
+        for _ in range(args.warmup):
+            pcie_step()
+        msp = time_loop(torch, pcie_step, args.steps)
+        extras["pcie_inclusive"] = {"ms": round(msp, 4), "pair_frames_per_s": round(T * P / (msp * 1e-3)),
+                                    "h2d_bytes": xh.numel() * 4, "d2h_bytes": oh.numel() * 4}
 
     cpu = None
     if not args.no_cpu:
