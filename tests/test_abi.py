@@ -265,3 +265,27 @@ def test_batch_classes_split_by_frame_size(fcc):
         assert lib.fcc_batch_query(h, ctypes.byref(info)) == 0
         assert info.num_classes == classes, sizes
         lib.fcc_batch_destroy(h)
+
+
+def test_batch_layout_with_arrays_without_frames(fcc):
+    """Arrays shorter than their frame size get no frames and no output span;
+    a negative length is refused."""
+    lib = fcc._lib.load()
+    xyz = square_array(0.05)
+    plans = [fcc.Plan(xyz, 16000.0, frame_size=N, hop=N // 4, rank=4, precision="fp16") for N in (512, 256, 512)]
+    n = len(plans)
+    hs = (ctypes.c_void_p * n)(*[p._h for p in plans])
+    for lengths, frames in [((511, 256, 0), (0, 1, 0)), ((0, 0, 0), (0, 0, 0)), ((512, 100, 640), (1, 0, 2))]:
+        h = ctypes.c_void_p()
+        assert lib.fcc_batch_create(hs, n, (ctypes.c_int64 * n)(*lengths), ctypes.byref(h)) == 0
+        info = fcc._lib.FccBatchInfo()
+        assert lib.fcc_batch_query(h, ctypes.byref(info)) == 0
+        ao, to, nf = (ctypes.c_int64 * n)(), (ctypes.c_int64 * n)(), (ctypes.c_int64 * n)()
+        assert lib.fcc_batch_layout(h, ao, to, nf) == 0
+        assert tuple(nf) == frames
+        assert list(to) == list(np.cumsum([0] + [T * p.P for T, p in zip(frames, plans)])[:-1])
+        assert info.tdoa_count == sum(T * p.P for T, p in zip(frames, plans))
+        assert info.audio_floats == sum(p.M * L for p, L in zip(plans, lengths))
+        lib.fcc_batch_destroy(h)
+    h = ctypes.c_void_p()
+    assert lib.fcc_batch_create(hs, n, (ctypes.c_int64 * n)(512, -1, 512), ctypes.byref(h)) == -1
