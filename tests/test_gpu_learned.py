@@ -72,7 +72,8 @@ def _forward_bound(theta, coef, H):
 
 
 @pytest.mark.parametrize("in_dim,H,rows", [(10, 128, 300), (22, 128, 1000), (18, 48, 77), (64, 512, 130),
-                                         (10, 32, 100), (40, 64, 333), (64, 128, 17)])
+                                         (10, 32, 100), (40, 64, 333), (64, 128, 17),
+                                         (10, 128, 1), (22, 64, 16), (18, 48, 1)])   # one row; one tile
 def test_forward_matches_oracle(torch, learned, in_dim, H, rows):
     theta = _theta(in_dim, H, 10 + in_dim)
     coef = _coef(rows, in_dim, 20 + rows)
