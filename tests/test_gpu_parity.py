@@ -409,3 +409,58 @@ def test_rank_and_size_limits(torch, fcc, M, N, tau_max, D, precision):
     assert e.max() <= tol
     rep = tdoa_report(t, y_ref, tau_max, tol)
     assert rep["mismatch_qualified"] == 0 and rep["invalid_elsewhere"] == 0, rep
+
+
+# ------------------------------------------------------ coefficients (eq. 9) --
+
+def _sigma_clusters(sigma, is_sym, rel=1e-6):
+    """Components of one parity whose singular values lie within rel sigma_0 of
+    their neighbour: inside such a cluster the basis vectors, and with them the
+    coefficients, are fixed only up to an orthogonal rotation."""
+    groups = []
+    for parity in (True, False):
+        cur = []
+        for k in [k for k in range(len(sigma)) if bool(is_sym[k]) == parity]:
+            if cur and sigma[cur[-1]] - sigma[k] > rel * sigma[0]:
+                groups.append(cur)
+                cur = []
+            cur.append(k)
+        if cur:
+            groups.append(cur)
+    return groups
+
+
+@pytest.mark.parametrize("config,seconds,D,r,precision", [(2, 1.0, 11, 1, "fp32"), (2, 1.0, 6, 1, "fp16"),
+                                                          (3, 0.3, 15, 1, "fp32"), (1, 1.0, 9, 2, "fp32")])
+def test_coefficients_match_oracle(torch, fcc, config, seconds, D, r, precision):
+    """fcc_coefficients against the oracle's z_k (eq. 9) on the same spectra,
+    (a_k, b_k) = (Re z_k, Im z_k).  An isolated component must match with its
+    sign; a cluster of equal singular values must match after the orthogonal
+    rotation that best aligns it (Procrustes).  Bar: per pair-frame within 1e-4
+    of max_k |z_k|."""
+    _say(f"coefficients config {config} D={D} r={r} {precision}")
+    rec = make_recording(config, seconds=seconds)
+    p = _plan(fcc, rec, D, interp=r, precision=precision)
+    X = O.stft(rec.x, rec.N, rec.hop)
+    B = O.fcc_basis(rec.N, p.tau_max, D, r)
+    from paper_2204_13622_amd import Plan
+    packed = Plan.pack_spectrum(O.phat(X)).astype(np.float16 if precision == "fp16" else np.float32)
+    e = Plan.unpack_spectrum(packed.astype(np.float64))
+    R = np.stack([e[:, i] * np.conj(e[:, j]) for i, j in O.mic_pairs(p.M)], axis=1)
+    z_ref = O.fcc_coefficients(R, B).reshape(-1, D)
+    spec = torch.from_numpy(packed).cuda().contiguous()
+    c = p.coefficients(spec).cpu().numpy().astype(np.float64)
+    assert c.shape == (len(X), p.P, 2 * D)
+    z = (c[..., 0::2] + 1j * c[..., 1::2]).reshape(-1, D)
+    aligned = np.empty_like(z)
+    groups = _sigma_clusters(B.sigma, B.is_sym)
+    for g in groups:
+        U, _, Vt = np.linalg.svd(np.real(z_ref[:, g].conj().T @ z[:, g]))
+        Q = U @ Vt                                         # z[:, g] ~ z_ref[:, g] Q
+        if len(g) == 1:
+            assert Q[0, 0] == 1.0, g                       # an isolated component keeps its sign
+        aligned[:, g] = z[:, g] @ Q.T
+    scale = np.abs(z_ref).max(-1)
+    err = np.abs(aligned - z_ref).max(-1) / np.where(scale > 0, scale, 1.0)
+    print(f"clusters {[len(g) for g in groups]}, max rel coefficient err {err.max():.3e}", flush=True)
+    assert err.max() <= EPS32
