@@ -185,6 +185,9 @@ fcc_status fcc_correlation(fcc_plan plan, const void* d_basis,
  *   d_coef [T][P][2D] FP32, (a_k, b_k) interleaved, components in the order
  *   of fcc_basis_export (symmetric, antisymmetric, ...).
  * The correlation is y(tau_i) = 2 sum_k (Dc(i,k) a_k - Ds(i,k) b_k).
+ * The coefficients refer to the plan's own basis (fcc_basis_export): where
+ * singular values of one parity coincide, any rotation of their vectors is an
+ * equally valid basis, and the planner's deterministic choice is the one used.
  * FCC method only; computed in FP32 from the spectra in any storage type. */
 fcc_status fcc_coefficients(fcc_plan plan, const void* d_basis, const void* d_spec,
                             int64_t num_frames, float* d_coef, hipStream_t stream);
