@@ -137,6 +137,27 @@ def test_gcc_shapes(torch, fcc, M, N, tau_max):
     _check_fp32(t.cpu().numpy(), y.cpu().numpy(), y_ref, tau_max)
 
 
+@pytest.mark.parametrize("M,N,tau_max,seconds", [(16, 512, 5, 1.0), (16, 2048, 30, 0.5)])
+def test_gcc_fp16_spectra(torch, fcc, M, N, tau_max, seconds):
+    """GCC on FP16-stored spectra (inverse FFT, and the direct eq. (2) kernel
+    where the spectra exceed the FFT kernel's LDS) against the oracle on the
+    same quantised spectra: the arithmetic after decoding is FP32."""
+    _say(f"GCC fp16 spectra M={M} N={N}")
+    from paper_2204_13622_amd import Plan
+    x = random_signals(500 + N, M, int(16000 * seconds))
+    p = fcc.Plan(circular_array(M, 0.05), 16000.0, frame_size=N, hop=N // 4, tau_max=tau_max, method="gcc",
+                 precision="fp16")
+    X = O.stft(x, N, N // 4)
+    packed = Plan.pack_spectrum(O.phat(X)).astype(np.float16)
+    e = Plan.unpack_spectrum(packed.astype(np.float64))
+    R = np.stack([e[:, i] * np.conj(e[:, j]) for i, j in O.mic_pairs(M)], axis=1)
+    y_ref = O.gcc_corr(R, N, tau_max)
+    spec = torch.from_numpy(packed).cuda().contiguous()
+    y = p.correlation(spec).cpu().numpy()
+    t = p.tdoa_from_spectra(spec).cpu().numpy()
+    _check_fp32(t, y, y_ref, tau_max)
+
+
 @pytest.mark.parametrize("config,seconds", [(1, 1.0), (2, 2.0)])
 def test_gcc_end_to_end(torch, fcc, config, seconds):
     _say(f"GCC end to end config {config}")
