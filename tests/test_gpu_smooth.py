@@ -152,6 +152,7 @@ def _smoothed_ref(x, N, hop, tau_max, D, r, alpha):
     dict(kind="rand", M=3, seconds=1.0, N=1024, hop=512, tau_max=12, D=20, r=1, alpha=0.2),
     dict(kind="rand", M=2, seconds=1.5, N=2048, hop=1024, tau_max=20, D=13, r=1, alpha=0.3),
     dict(kind="rand", M=3, seconds=0.5, N=512, hop=256, tau_max=10, D=17, r=1, alpha=0.25),
+    dict(kind="rand", M=3, seconds=0.5, N=512, hop=256, tau_max=9, D=13, r=4, alpha=0.3),   # I = 73: five lag slots
 ])
 def test_smoothed_matches_oracle(torch, fcc, case):
     _say(f"smoothed {case}")
