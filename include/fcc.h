@@ -259,7 +259,9 @@ fcc_status fcc_doa(fcc_plan plan, const float* d_y, int64_t num_frames, const fl
  * fcc_batch_tune times candidate pair-stage launch shapes on the given buffers
  * and keeps the fastest.
  * Limits: every plan FP16 or BF16 storage (the same), method FCC, alpha = 1,
- * M <= 16, N >= 32, I <= 48, rank <= 32 (FCC_ERR_UNSUPPORTED otherwise).
+ * M <= 16, N >= 32, I <= 48, rank <= 32, and a class's tables plus two
+ * wavefront slabs within 160 KB of LDS (FCC_ERR_UNSUPPORTED otherwise; e.g.
+ * N = 1024 with rank 32 and I > 32 exceeds it).
  * Plans are copied; num_samples[a] fixes array a's length L_a at creation.
  * An array shorter than its frame size has no frames (T_a = 0) and no output;
  * when no array has a frame, fcc_batch_tdoa and fcc_batch_tune do nothing.

@@ -695,6 +695,9 @@ fcc_status fcc_batch_create(const fcc_plan* plans, int32_t num_arrays, const int
       c.head_words_max = std::max(c.head_words_max, fcc::batch_head_words(4 * c.kb, d.N / 2, c.tt, d.P));
       c.slab_words_max = std::max(c.slab_words_max, fcc::batch_slab_words(d.N, d.I));
     }
+    // the launcher's own condition: two wavefronts' slabs beside the tables
+    if (sizeof(uint32_t) * (size_t(c.head_words_max) + 2 * size_t(c.slab_words_max)) > 160 * 1024)
+      return fail(FCC_ERR_UNSUPPORTED, "a class's tables and two wavefront slabs exceed 160 KB of LDS");
     b->classes.push_back(c);
     prefixes.push_back(std::move(c_prefix));
   }

@@ -247,6 +247,10 @@ def test_batch_validation_and_layout(fcc):
     big = fcc.Plan(circular_array(17, 0.05), 16000.0, precision="fp16")
     hs = (ctypes.c_void_p * 1)(big._h)
     assert lib.fcc_batch_create(hs, 1, (ctypes.c_int64 * 1)(1000), ctypes.byref(h)) == -2
+    # rank 32, three lag tiles at N = 1024: the tables and two slabs exceed 160 KB of LDS
+    wide = fcc.Plan(circular_array(4, 0.05), 16000.0, frame_size=1024, hop=256, tau_max=20, rank=32, precision="fp16")
+    hs = (ctypes.c_void_p * 1)(wide._h)
+    assert lib.fcc_batch_create(hs, 1, (ctypes.c_int64 * 1)(4800), ctypes.byref(h)) == -2
 
 
 def test_batch_classes_split_by_frame_size(fcc):

@@ -115,3 +115,35 @@ def test_batch_short_and_empty_arrays(torch, fcc):
         assert [tuple(t.shape) for t in parts] == [(0, plans[0].P), (0, plans[1].P)]
     assert len(empty.tune(audio)["pair_classes"]) == empty.info.num_classes
     torch.cuda.synchronize()
+
+
+def test_batch_wide_tiles(torch, fcc):
+    """Classes of three lag tiles (I = 41, 47) and six or eight blocks of four
+    components (ranks 20-32), two arrays sharing one class, beside narrow
+    ones: every array equals the single-array path bit for bit.  A class
+    whose tables and two wavefront slabs exceed the LDS is refused at
+    creation."""
+    _say("batch with wide tiles")
+    from gen import circular_array, random_signals
+    too_big = fcc.Plan(circular_array(4, 0.05), 16000.0, frame_size=1024, hop=256, tau_max=20, rank=32,
+                       precision="fp16")
+    with pytest.raises(fcc.FccError) as ei:
+        fcc.Batch([too_big], [4800])
+    assert ei.value.name == "FCC_ERR_UNSUPPORTED"
+    shapes = [(4, 512, 20, 32), (5, 512, 20, 30), (6, 512, 20, 24), (3, 1024, 23, 20), (8, 512, 10, 12),
+              (16, 256, 5, 6)]
+    plans, xs = [], []
+    for k, (M, N, tau_max, D) in enumerate(shapes):
+        plans.append(fcc.Plan(circular_array(M, 0.05), 16000.0, frame_size=N, hop=N // 4, tau_max=tau_max,
+                              rank=D, precision="fp16"))
+        xs.append(random_signals(4400 + k, M, 4800 + 37 * k))
+    b = fcc.Batch(plans, [x.shape[1] for x in xs])
+    assert b.info.num_classes == 5
+    audio = b.pack([torch.from_numpy(x) for x in xs])
+    expect = [p.tdoa(torch.from_numpy(x).cuda()).cpu().numpy() for p, x in zip(plans, xs)]
+    for graph in (False, True):
+        for a, (g, e) in enumerate(zip(b.split(b.tdoa(audio, graph=graph)), expect)):
+            assert np.array_equal(g.cpu().numpy(), e), (graph, a)
+    b.tune(audio)
+    for a, (g, e) in enumerate(zip(b.split(b.tdoa(audio, graph=True)), expect)):
+        assert np.array_equal(g.cpu().numpy(), e), ("tuned", a)

@@ -405,7 +405,8 @@ def test_mfma_pair_stage_fp16(torch, fcc, config, seconds, D, M):
 # form), 5e-3 on the matrix cores
 @pytest.mark.parametrize("M,N,tau_max,D,precision,tol", [
     (3, 512, 48, 64, "fp32", EPS32),    # largest rank: the fold kernel with 64 components, I = 97
-    (4, 1024, 20, 32, "fp16", 5e-3),    # largest matrix-core rank: eight blocks of four, three lag tiles
+    (4, 512, 20, 32, "fp16", 5e-3),     # largest matrix-core rank: eight blocks of four, three lag tiles
+    (4, 1024, 20, 32, "fp16", EPS32),   # the same at N = 1024 exceeds the matrix-core LDS: the direct form
     (20, 512, 20, 16, "fp16", EPS32),   # more than 16 microphones: the direct form
     (4, 512, 24, 40, "fp16", EPS32),    # rank above 32 and I = 49: the direct form
     (32, 512, 20, 24, "fp16", EPS32),   # 32 microphones: 496 pairs over 256 threads, 78 KB of LDS
