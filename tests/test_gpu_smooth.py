@@ -253,3 +253,8 @@ def test_smoothed_errors(torch, fcc):
         q.tdoa_smoothed(q.spectra(_dev(torch, _two_mic(1))))
     out = p.tdoa_smoothed(spec[:0])                        # no frames: nothing to do, state untouched
     assert out["tdoa"].shape == (0, 1) and float(out["state"].abs().max()) == 0.0
+    # rank above 32: outside the smoothing kernels, refused before any launch
+    w = fcc.Plan(PAIR_15CM, 16000.0, frame_size=512, hop=256, tau_max=24, rank=40, alpha=0.1)
+    with pytest.raises(fcc.FccError) as ei:
+        w.tdoa_smoothed(w.spectra(_dev(torch, _two_mic(2))))
+    assert ei.value.name == "FCC_ERR_UNSUPPORTED"
