@@ -36,6 +36,52 @@ def _ptr(t) -> ctypes.c_void_p:
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _same_device(a, b) -> bool:
+    torch = _torch()
+    a, b = torch.device(a), torch.device(b)
+    if a.type != b.type:
+        return False
+    if a.type != "cuda":
+        return True
+    cur = torch.cuda.current_device() if torch.cuda.is_available() else 0
+    return (a.index if a.index is not None else cur) == (b.index if b.index is not None else cur)
+
+
+def check_out(t, shape, dtype, device, name: str = "out"):
+    """A caller-supplied output tensor: the exact shape, dtype, device and a
+    contiguous layout, since the library writes every element of that shape
+    through a bare pointer.  Raises ValueError before anything is launched."""
+    torch = _torch()
+    shape = tuple(int(v) for v in shape)
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if tuple(t.shape) != shape:
+        raise ValueError(f"{name} must have shape {list(shape)}, got {list(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if not _same_device(t.device, device):
+        raise ValueError(f"{name} must be on {device}, got {t.device}")
+    return t
+
+
+def check_workspace(ws, nbytes: int, device, name: str = "workspace"):
+    """A caller-supplied scratch buffer: contiguous, on `device`, holding at
+    least `nbytes` bytes.  Raises ValueError before anything is launched."""
+    torch = _torch()
+    if not isinstance(ws, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor")
+    if not ws.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if not _same_device(ws.device, device):
+        raise ValueError(f"{name} must be on {device}, got {ws.device}")
+    have = ws.numel() * ws.element_size()
+    if have < int(nbytes):
+        raise ValueError(f"{name} holds {have} bytes, {int(nbytes)} needed")
+    return ws
+
+
 class Plan:
     """One array geometry: FP64 basis built on the host, tables on each device.
 
@@ -164,6 +210,8 @@ class Plan:
             out["y"] = torch.empty((T, self.P, self.I), dtype=torch.float32, device=dev)
         if workspace is None:
             workspace = torch.empty(max(self.smooth_workspace_bytes(T), 256), dtype=torch.uint8, device=dev)
+        else:
+            check_workspace(workspace, self.smooth_workspace_bytes(T), dev)
         null = ctypes.c_void_p(0)
         basis = self.basis_tensor(dev)
         with torch.cuda.device(dev):
@@ -244,6 +292,8 @@ class Plan:
         T = self.num_frames(L)
         if out is None:
             out = torch.empty((T, self.M, self.N // 2, 2), dtype=self.spectrum_dtype(), device=x.device)
+        else:
+            check_out(out, (T, self.M, self.N // 2, 2), self.spectrum_dtype(), x.device)
         basis = self.basis_tensor(x.device)
         with torch.cuda.device(x.device):
             _lib.check(self._lib.fcc_spectra(self._h, _ptr(basis), _ptr(x), L, ld, _ptr(out),
@@ -257,9 +307,13 @@ class Plan:
         T = self.num_frames(L)
         if out is None:
             out = torch.empty((T, self.P), dtype=torch.int32, device=x.device)
+        else:
+            check_out(out, (T, self.P), torch.int32, x.device)
         if workspace is None:
             workspace = torch.empty(max(self.workspace_bytes(T), 256), dtype=torch.uint8,
                                     device=x.device)
+        else:
+            check_workspace(workspace, self.workspace_bytes(T), x.device)
         basis = self.basis_tensor(x.device)
         with torch.cuda.device(x.device):
             _lib.check(self._lib.fcc_tdoa(self._h, _ptr(basis), _ptr(x), L, ld, _ptr(out),
@@ -281,6 +335,8 @@ class Plan:
         T = self._check_spec(spec)
         if out is None:
             out = torch.empty((T, self.P), dtype=torch.int32, device=spec.device)
+        else:
+            check_out(out, (T, self.P), torch.int32, spec.device)
         basis = self.basis_tensor(spec.device)
         with torch.cuda.device(spec.device):
             _lib.check(self._lib.fcc_tdoa_from_spectra(self._h, _ptr(basis), _ptr(spec), T,
@@ -293,6 +349,8 @@ class Plan:
         T = self._check_spec(spec)
         if out is None:
             out = torch.empty((T, self.P, self.I), dtype=torch.float32, device=spec.device)
+        else:
+            check_out(out, (T, self.P, self.I), torch.float32, spec.device)
         basis = self.basis_tensor(spec.device)
         with torch.cuda.device(spec.device):
             _lib.check(self._lib.fcc_correlation(self._h, _ptr(basis), _ptr(spec), T, _ptr(out),
@@ -305,6 +363,8 @@ class Plan:
         T = self._check_spec(spec)
         if out is None:
             out = torch.empty((T, self.P, 2 * self.rank), dtype=torch.float32, device=spec.device)
+        else:
+            check_out(out, (T, self.P, 2 * self.rank), torch.float32, spec.device)
         basis = self.basis_tensor(spec.device)
         with torch.cuda.device(spec.device):
             _lib.check(self._lib.fcc_coefficients(self._h, _ptr(basis), _ptr(spec), T, _ptr(out),
@@ -317,6 +377,8 @@ class Plan:
         T = self._check_spec(spec)
         if out is None:
             out = torch.empty((T, self.P), dtype=torch.float32, device=spec.device)
+        else:
+            check_out(out, (T, self.P), torch.float32, spec.device)
         basis = self.basis_tensor(spec.device)
         with torch.cuda.device(spec.device):
             _lib.check(self._lib.fcc_tdoa_parabolic(self._h, _ptr(basis), _ptr(spec), T, _ptr(out),

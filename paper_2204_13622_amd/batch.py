@@ -68,12 +68,27 @@ class Batch:
             out[o:o + x.numel()].copy_(x.reshape(-1).to(self.device))
         return out
 
-    def tdoa(self, audio, out=None, graph=True):
+    def _check_audio(self, audio):
         torch = _torch()
-        if audio.dtype != torch.float32 or not audio.is_contiguous() or audio.device != self.device:
+        if (not isinstance(audio, torch.Tensor) or audio.dtype != torch.float32 or not audio.is_contiguous()
+                or audio.device != self.device):
             raise ValueError("audio must be the packed float32 buffer on the batch's device")
         if audio.numel() < self.info.audio_floats:
             raise ValueError("audio buffer too small")
+
+    def _check_out(self, out):
+        torch = _torch()
+        if (not isinstance(out, torch.Tensor) or out.dtype != torch.int32 or not out.is_contiguous()
+                or out.device != self.device):
+            raise ValueError("out must be a contiguous int32 tensor on the batch's device")
+        if out.numel() < self.info.tdoa_count:
+            raise ValueError(f"out holds {out.numel()} values, {self.info.tdoa_count} needed")
+
+    def tdoa(self, audio, out=None, graph=True):
+        torch = _torch()
+        self._check_audio(audio)
+        if out is not None:
+            self._check_out(out)
         if out is None:
             # one output buffer per batch, so a captured graph is reused; the
             # next call overwrites it unless `out` is given
@@ -90,8 +105,11 @@ class Batch:
         """Times candidate pair-stage tile shapes on these buffers and keeps
         the fastest; returns the shapes in use."""
         torch = _torch()
+        self._check_audio(audio)
         if out is None:
             out = torch.empty(max(self.info.tdoa_count, 1), dtype=torch.int32, device=self.device)
+        else:
+            self._check_out(out)
         with torch.cuda.device(self.device):
             _lib.check(self._lib.fcc_batch_tune(self._h, _ptr(self.image), _ptr(audio), _ptr(out),
                                                 _ptr(self.workspace), _stream_handle(self.device)))

@@ -265,7 +265,10 @@ static fcc_status pair_stage(const fcc::Plan& p, const void* d_basis, const void
     e = fcc::launch_pair_fold32(a);
   } else if (fcc::gcc_ifft_supported(a)) e = fcc::launch_gcc_ifft(a);
   else if (fcc::pair_mfma_supported(a)) e = fcc::launch_pair_mfma(a);
-  else if (p.precision == FCC_FP32 && fcc::pair_fold32_supported(a)) e = fcc::launch_pair_fold32(a);
+  // FP32 spectra take the fold kernel; 16-bit and 8-bit spectra the direct
+  // form, unless its lag registers cannot hold the window (I > 64)
+  else if (fcc::pair_fold32_supported(a) && (p.precision == FCC_FP32 || !fcc::pair_valu_supported(a)))
+    e = fcc::launch_pair_fold32(a);
   else e = fcc::launch_pair_valu(a);
   if (e == hipErrorInvalidValue)
     return set_error(FCC_ERR_UNSUPPORTED, "shape outside the pair kernel's limits");

@@ -157,6 +157,7 @@ hipError_t mlp_select(const float* out, const float* fallback, int64_t rows, flo
 hipError_t mlp_adam(float* theta, float* m, float* v, const float* grad, int64_t n, float lr, float b1, float b2,
                     float eps, int step, hipStream_t st);
 hipError_t launch_pair_valu(const PairArgs& a);
+bool pair_valu_supported(const PairArgs& a);
 bool pair_mfma_supported(const PairArgs& a);
 bool pair_fold32_supported(const PairArgs& a);
 hipError_t launch_pair_fold32(const PairArgs& a);

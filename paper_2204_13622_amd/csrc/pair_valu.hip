@@ -156,6 +156,10 @@ size_t pair_valu_lds_bytes(int M, int N, int D) {
   return sizeof(float2) * size_t(M) * (N / 2 + 1) + sizeof(float) * size_t(D) * (N / 4 + 1);
 }
 
+bool pair_valu_supported(const PairArgs& a) {
+  return a.I <= 64 && pair_valu_lds_bytes(a.M, a.N, a.method == FCC_METHOD_GCC ? 0 : a.D) <= 160 * 1024;
+}
+
 hipError_t launch_pair_valu(const PairArgs& a) {
   if (a.T == 0) return hipSuccess;
   const size_t lds = pair_valu_lds_bytes(a.M, a.N, a.method == FCC_METHOD_GCC ? 0 : a.D);   // GCC stages no basis

@@ -21,7 +21,7 @@ import math
 import numpy as np
 
 from . import _lib
-from . import _ptr, _stream_handle, _torch
+from . import _ptr, _stream_handle, _torch, check_out, check_workspace
 
 __all__ = ["Mlp", "num_params", "init_params", "tdoa_learned", "learned_workspace_bytes",
            "choose_threshold"]
@@ -95,6 +95,8 @@ class Mlp:
         R = self._check_rows(coef)
         if out is None:
             out = torch.empty(tuple(coef.shape[:-1]) + (2,), dtype=torch.float32, device=self.device)
+        else:
+            check_out(out, tuple(coef.shape[:-1]) + (2,), torch.float32, self.device)
         ws = self._workspace(R)
         with torch.cuda.device(self.device):
             _lib.check(self._lib.fcc_mlp_forward(_ptr(self.params), self.in_dim, self.hidden, _ptr(coef), R,
@@ -108,8 +110,12 @@ class Mlp:
         R = self._check_rows(coef)
         if target.dtype != torch.float32 or not target.is_contiguous() or target.numel() != R:
             raise ValueError("target must be contiguous float32 with one value per row")
+        if target.device != self.device:
+            raise ValueError("target must be on the network's device")
         if out is None:
             out = torch.empty((R, 2), dtype=torch.float32, device=self.device)
+        else:
+            check_out(out, (R, 2), torch.float32, self.device)
         ws = self._workspace(R)
         self.loss_sum.zero_()
         with torch.cuda.device(self.device):
@@ -172,11 +178,17 @@ def tdoa_learned(plan, spec, mlp: Mlp, min_confidence: float, tau=None, confiden
         raise ValueError("network input must be 2 * rank on the spectra's device")
     if tau is None:
         tau = torch.empty((T, plan.P), dtype=torch.float32, device=spec.device)
+    else:
+        check_out(tau, (T, plan.P), torch.float32, spec.device, "tau")
     if confidence is None:
         confidence = torch.empty((T, plan.P), dtype=torch.float32, device=spec.device)
+    else:
+        check_out(confidence, (T, plan.P), torch.float32, spec.device, "confidence")
     if workspace is None:
         workspace = torch.empty(max(learned_workspace_bytes(plan, mlp.hidden, T), 256), dtype=torch.uint8,
                                 device=spec.device)
+    else:
+        check_workspace(workspace, learned_workspace_bytes(plan, mlp.hidden, T), spec.device)
     basis = plan.basis_tensor(spec.device)
     with torch.cuda.device(spec.device):
         _lib.check(plan._lib.fcc_tdoa_learned(plan._h, _ptr(basis), _ptr(spec), T, _ptr(mlp.params),

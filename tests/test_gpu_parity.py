@@ -216,6 +216,96 @@ def test_full_size_config2_sampled(torch, fcc):
         _check_fp32(t.cpu().numpy()[frames], y.cpu().numpy()[frames], y_ref, p.tau_max)
 
 
+def _quantize(packed, precision):
+    """Packed FP64 spectra rounded to a storage type on the host (round to
+    nearest even), returned as (device tensor in that type, FP64 values)."""
+    import torch as _t
+    dt = {"fp16": _t.float16, "bf16": _t.bfloat16, "fp8": _t.float8_e4m3fn}[precision]
+    q = _t.from_numpy(np.ascontiguousarray(packed, dtype=np.float32)).to(dt)
+    return q.cuda().contiguous(), q.to(_t.float64).numpy()
+
+
+@pytest.fixture(scope="module")
+def rec2_full():
+    """The benchmark workload (60 s, 16 microphones on a 5 cm circle, 16 kHz,
+    N = 512, hop 128: T = 7497 frames, 120 pairs) and its FP64 whitened
+    spectra in the packed layout."""
+    from paper_2204_13622_amd import Plan
+    rec = make_recording(2)
+    X = O.stft(rec.x, rec.N, rec.hop)
+    packed = Plan.pack_spectrum(O.phat(X))
+    del X
+    return rec, packed
+
+
+@pytest.mark.parametrize("precision,D,min_agree,max_err", [
+    ("fp16", 11, 0.995, 5e-3), ("fp16", 6, 0.995, 5e-3), ("bf16", 11, 0.98, 3e-2), ("bf16", 6, 0.98, 3e-2),
+    ("fp8", 11, 0.90, 0.3), ("fp8", 6, 0.90, 0.3)])
+def test_full_size_headline_16bit(torch, fcc, rec2_full, precision, D, min_agree, max_err):
+    """The benchmarked call at full size: fcc_tdoa on 60 s of the benchmark
+    workload, T = 7497 frames.  The pair stage's persistent grid holds
+    2 x CUs workgroups of 4 wavefronts, so every wavefront walks 3-4 frames
+    and the next-frame prefetch runs.
+
+    (1) Same operands: the oracle's whitened spectra, rounded to the storage
+        type on the host, go through fcc_correlation / fcc_tdoa_from_spectra
+        (the launch shape fcc_tdoa uses at this T); sampled frames are compared
+        with the FP64 correlation of those rounded spectra at 5e-3, the
+        integer lags bit-exact where the top two values are 1e-2 max|y| apart.
+    (2) fcc_tdoa on the audio equals fcc_tdoa_from_spectra(fcc_spectra(x))
+        on every pair-frame (the same kernels).
+    (3) Against the FP64 oracle on the unquantised audio: agreement rate and
+        maximum relative correlation error, bounded per storage type."""
+    rec, packed = rec2_full
+    _say(f"headline full size: config 2, T=7497, {precision}, D={D}")
+    p = _plan(fcc, rec, D, precision=precision)
+    T = p.num_frames(rec.L)
+    assert T == 7497 and p.P == 120 and p.I == 11
+    rng = np.random.default_rng(2200 + D)
+    frames = np.unique(np.concatenate([[0, 1, T - 2, T - 1], rng.choice(T, 60, replace=False)]))
+    B = O.fcc_basis(rec.N, p.tau_max, D)
+
+    # (1) same operands
+    spec_q, e_q = _quantize(packed, precision)
+    y = p.correlation(spec_q)
+    t = p.tdoa_from_spectra(spec_q)
+    torch.cuda.synchronize()
+    assert tuple(y.shape) == (T, 120, 11) and tuple(t.shape) == (T, 120)
+    e = fcc.Plan.unpack_spectrum(e_q[frames])
+    R = np.stack([e[:, i] * np.conj(e[:, j]) for i, j in O.mic_pairs(16)], axis=1)
+    y_ref = O.fcc_corr(R, B)
+    y_s, t_s = y.cpu().numpy()[frames], t.cpu().numpy()[frames]
+    del y, spec_q
+    err = corr_errors(y_s, y_ref)
+    rep = tdoa_report(t_s, y_ref, p.tau_max, 5e-3)
+    print(f"[same operands {precision} D={D}] max rel corr err {err.max():.3e}, "
+          f"agreement {rep['agreement']:.5f} ({rep['qualified']} qualified)", flush=True)
+    assert err.max() < 5e-3
+    assert rep["mismatch_qualified"] == 0, rep
+    assert rep["invalid_elsewhere"] == 0, rep
+
+    # (2) the benchmarked entry point runs the same kernels
+    x = _dev(torch, rec.x)
+    t_full = p.tdoa(x)
+    spec = p.spectra(x)
+    t_two = p.tdoa_from_spectra(spec)
+    y = p.correlation(spec)
+    torch.cuda.synchronize()
+    assert torch.equal(t_full, t_two)
+
+    # (3) against the FP64 oracle on the unquantised audio
+    t_ref, y_ref = O.fcc_tdoa(rec.x, rec.N, rec.hop, p.tau_max, D, frames=frames, return_corr=True)
+    y_s, t_s = y.cpu().numpy()[frames], t_full.cpu().numpy()[frames]
+    del y, spec
+    e = corr_errors(y_s, y_ref)
+    rep = tdoa_report(t_s, y_ref, p.tau_max, float(e.max()))
+    print(f"[fp64 oracle {precision} D={D}] agreement {rep['agreement']:.5f} max rel err {e.max():.3e} "
+          f"mean {e.mean():.3e}", flush=True)
+    assert rep["agreement"] >= min_agree
+    assert e.max() <= max_err
+    assert rep["mismatch_qualified"] == 0
+
+
 @pytest.fixture(scope="module")
 def rec3():
     return make_recording(3)                   # 120 s, 16 mics, 48 kHz: T = 22497 frames
@@ -410,6 +500,7 @@ def test_mfma_pair_stage_fp16(torch, fcc, config, seconds, D, M):
     (20, 512, 20, 16, "fp16", EPS32),   # more than 16 microphones: the direct form
     (4, 512, 24, 40, "fp16", EPS32),    # rank above 32 and I = 49: the direct form
     (32, 512, 20, 24, "fp16", EPS32),   # 32 microphones: 496 pairs over 256 threads, 78 KB of LDS
+    (4, 512, 40, 32, "fp16", EPS32),    # I = 81 > 64 at 16-bit storage: the fold kernel
 ])
 def test_rank_and_size_limits(torch, fcc, M, N, tau_max, D, precision, tol):
     _say(f"limits M={M} N={N} tau_max={tau_max} D={D} {precision}")
@@ -488,3 +579,37 @@ def test_coefficients_match_oracle(torch, fcc, config, seconds, D, r, precision)
     err = np.abs(aligned - z_ref).max(-1) / np.where(scale > 0, scale, 1.0)
     print(f"clusters {[len(g) for g in groups]}, max rel coefficient err {err.max():.3e}", flush=True)
     assert err.max() <= EPS32
+
+
+def test_wrong_outputs_refused(torch, fcc):
+    """Caller-supplied outputs and workspaces of the wrong shape, type or size
+    are refused on the host, before any launch; correct ones are used."""
+    _say("binding: wrong out / workspace refused")
+    rec = make_recording(1)
+    p = _plan(fcc, rec, 9, precision="fp16")
+    x = _dev(torch, rec.x)
+    T = p.num_frames(rec.L)
+    spec = p.spectra(x)
+    bad_outs = [torch.empty((T - 1, p.P), dtype=torch.int32, device="cuda"),
+                torch.empty((T, p.P), dtype=torch.int64, device="cuda"),
+                torch.empty((p.P, T), dtype=torch.int32, device="cuda").t(),
+                torch.empty((T, p.P), dtype=torch.int32)]
+    for bad in bad_outs:
+        with pytest.raises(ValueError):
+            p.tdoa(x, out=bad)
+        with pytest.raises(ValueError):
+            p.tdoa_from_spectra(spec, out=bad)
+    with pytest.raises(ValueError):
+        p.tdoa(x, workspace=torch.empty(p.workspace_bytes(T) - 1, dtype=torch.uint8, device="cuda"))
+    with pytest.raises(ValueError):
+        p.correlation(spec, out=torch.empty((T, p.P, p.I - 1), dtype=torch.float32, device="cuda"))
+    with pytest.raises(ValueError):
+        p.spectra(x, out=torch.empty((T, p.M, p.N // 2, 2), dtype=torch.float32, device="cuda"))
+    with pytest.raises(ValueError):
+        p.coefficients(spec, out=torch.empty((T, p.P, 2 * p.rank + 2), dtype=torch.float32, device="cuda"))
+    with pytest.raises(ValueError):
+        p.tdoa_parabolic(spec, out=torch.empty((T, p.P), dtype=torch.int32, device="cuda"))
+    out = torch.full((T, p.P), 99, dtype=torch.int32, device="cuda")
+    ws = torch.empty(p.workspace_bytes(T), dtype=torch.uint8, device="cuda")
+    assert p.tdoa(x, out=out, workspace=ws) is out
+    assert torch.equal(out, p.tdoa_from_spectra(spec))
