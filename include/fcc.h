@@ -163,6 +163,26 @@ fcc_status fcc_tdoa(fcc_plan plan, const void* d_basis, const float* d_x,
                     int64_t num_samples, int64_t ld, int32_t* d_tdoa,
                     void* d_workspace, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): fcc_tdoa
+ * with no workspace argument.  The spectra are staged in a static device
+ * array of FCC_NOALLOC_SCRATCH_BYTES bytes that the library holds on each
+ * GPU it runs on until the process ends; the frames are processed in chunks
+ * of floor(FCC_NOALLOC_SCRATCH_BYTES / info.spectrum_bytes_per_frame) frames,
+ * each chunk through the same kernels as fcc_tdoa, so d_tdoa equals
+ * fcc_tdoa's output bit for bit.  No call allocates memory.
+ *   d_x [M][ld] FP32 audio, d_tdoa [T][P] int32 (caller-owned, as fcc_tdoa).
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (other streams or threads) race and must be serialised by the caller.
+ * Errors: those of fcc_tdoa; FCC_ERR_UNSUPPORTED for alpha < 1 plans (the
+ * recursion's state and carries need fcc_tdoa's workspace) and for a plan
+ * whose single frame of spectra exceeds FCC_NOALLOC_SCRATCH_BYTES;
+ * FCC_ERR_HIP if the array's device address cannot be obtained. */
+#define FCC_NOALLOC_SCRATCH_BYTES (64u << 20)
+fcc_status fcc_tdoa_noalloc(fcc_plan plan, const void* d_basis, const float* d_x,
+                            int64_t num_samples, int64_t ld, int32_t* d_tdoa,
+                            hipStream_t stream);
+
 /* Pairs, fold (eq. 8), projection (eq. 9), expansion 2 Re{U z} to the I lags
  * and argmax (first index on ties), from whitened spectra laid out as
  * fcc_spectra writes them; d_tdoa [T][P] int32 in units of 1/r sample.  With

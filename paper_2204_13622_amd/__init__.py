@@ -320,6 +320,23 @@ class Plan:
                                           _ptr(workspace), _stream_handle(x.device)))
         return out
 
+    def tdoa_noalloc(self, x, out=None):
+        """fcc_tdoa without a workspace: the library stages the spectra in its
+        static per-GPU array (64 MiB) in chunks of frames.  Calls that overlap
+        on one GPU race on that array."""
+        torch = _torch()
+        L, ld = self._check_audio(x)
+        T = self.num_frames(L)
+        if out is None:
+            out = torch.empty((T, self.P), dtype=torch.int32, device=x.device)
+        else:
+            check_out(out, (T, self.P), torch.int32, x.device)
+        basis = self.basis_tensor(x.device)
+        with torch.cuda.device(x.device):
+            _lib.check(self._lib.fcc_tdoa_noalloc(self._h, _ptr(basis), _ptr(x), L, ld, _ptr(out),
+                                                  _stream_handle(x.device)))
+        return out
+
     def _check_spec(self, spec):
         torch = _torch()
         if not isinstance(spec, torch.Tensor) or spec.device.type != "cuda":

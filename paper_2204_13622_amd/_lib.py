@@ -8,6 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libfcc.so")
 
 FCC_OK = 0
+NOALLOC_SCRATCH_BYTES = 64 << 20      # FCC_NOALLOC_SCRATCH_BYTES
 STATUS_NAMES = {0: "FCC_OK", -1: "FCC_ERR_INVALID_ARG", -2: "FCC_ERR_UNSUPPORTED",
                 -3: "FCC_ERR_BASIS_AMBIGUOUS", -4: "FCC_ERR_HIP", -5: "FCC_ERR_INTERNAL"}
 PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2, "fp8": 3, "fp8_e4m3": 3}
@@ -15,7 +16,7 @@ METHODS = {"fcc": 0, "gcc": 1}
 
 # every symbol include/fcc.h declares
 EXPORTS = ("fcc_plan_create", "fcc_plan_destroy", "fcc_plan_query", "fcc_plan_upload",
-           "fcc_num_frames", "fcc_workspace_bytes", "fcc_spectra", "fcc_tdoa",
+           "fcc_num_frames", "fcc_workspace_bytes", "fcc_spectra", "fcc_tdoa", "fcc_tdoa_noalloc",
            "fcc_tdoa_from_spectra", "fcc_correlation", "fcc_coefficients", "fcc_tdoa_parabolic",
            "fcc_basis_export", "fcc_mlp_num_params", "fcc_mlp_workspace_bytes", "fcc_mlp_forward",
            "fcc_mlp_backward", "fcc_mlp_adam", "fcc_learned_workspace_bytes", "fcc_tdoa_learned",
@@ -86,6 +87,7 @@ def load() -> ctypes.CDLL:
         "fcc_workspace_bytes": [vp, i64, ctypes.POINTER(ctypes.c_size_t)],
         "fcc_spectra": [vp, vp, vp, i64, i64, vp, vp],
         "fcc_tdoa": [vp, vp, vp, i64, i64, vp, vp, vp],
+        "fcc_tdoa_noalloc": [vp, vp, vp, i64, i64, vp, vp],
         "fcc_tdoa_from_spectra": [vp, vp, vp, i64, vp, vp],
         "fcc_correlation": [vp, vp, vp, i64, vp, vp],
         "fcc_coefficients": [vp, vp, vp, i64, vp, vp],

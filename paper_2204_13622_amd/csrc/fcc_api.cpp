@@ -369,6 +369,34 @@ fcc_status fcc_tdoa(fcc_plan plan, const void* d_basis, const float* d_x, int64_
   return pair_stage(p, d_basis, d_workspace, T, d_tdoa, nullptr, stream);
 }
 
+fcc_status fcc_tdoa_noalloc(fcc_plan plan, const void* d_basis, const float* d_x, int64_t num_samples,
+                            int64_t ld, int32_t* d_tdoa, hipStream_t stream) {
+  if (!plan) return set_error(FCC_ERR_INVALID_ARG, "NULL plan");
+  const fcc::Plan& p = plan->p;
+  fcc_status st = check_basis(d_basis);
+  if (st == FCC_OK) st = check_audio(p, d_x, num_samples, ld);
+  if (st != FCC_OK) return st;
+  if (p.alpha < 1.0f)
+    return set_error(FCC_ERR_UNSUPPORTED, "alpha < 1 needs fcc_tdoa's workspace for the recursion");
+  const int64_t T = frames_of(p, num_samples);
+  if (T == 0) return FCC_OK;
+  if (!d_tdoa) return set_error(FCC_ERR_INVALID_ARG, "d_tdoa is NULL");
+  if (!aligned(d_tdoa, 4)) return set_error(FCC_ERR_INVALID_ARG, "d_tdoa misaligned");
+  const size_t frame_bytes = size_t(p.M) * (p.N / 2) * p.spec_elem;
+  if (frame_bytes > size_t(FCC_NOALLOC_SCRATCH_BYTES))
+    return set_error(FCC_ERR_UNSUPPORTED, "one frame of spectra exceeds FCC_NOALLOC_SCRATCH_BYTES");
+  void* scratch = nullptr;
+  if ((st = hip_status(fcc::noalloc_scratch(&scratch), "static scratch address")) != FCC_OK) return st;
+  const int64_t chunk = int64_t(size_t(FCC_NOALLOC_SCRATCH_BYTES) / frame_bytes);
+  for (int64_t t0 = 0; t0 < T; t0 += chunk) {
+    const int64_t tc = T - t0 < chunk ? T - t0 : chunk;
+    const int64_t Lc = (tc - 1) * p.hop + p.N;             // exactly tc frames
+    if ((st = run_spectra(p, d_basis, d_x + t0 * p.hop, Lc, ld, scratch, stream)) != FCC_OK) return st;
+    if ((st = pair_stage(p, d_basis, scratch, tc, d_tdoa + t0 * p.P, nullptr, stream)) != FCC_OK) return st;
+  }
+  return FCC_OK;
+}
+
 fcc_status fcc_smooth_workspace_bytes(fcc_plan plan, int64_t num_frames, size_t* bytes) {
   if (!plan || !bytes) return set_error(FCC_ERR_INVALID_ARG, "NULL argument");
   if (num_frames < 0) return set_error(FCC_ERR_INVALID_ARG, "num_frames must be >= 0");

@@ -170,5 +170,7 @@ hipError_t launch_doa(const DoaArgs& a);
 hipError_t launch_fill_zero(float* p, int64_t n, hipStream_t stream);   // a fill kernel, safe under graph capture
 hipError_t launch_gcc_ifft(const PairArgs& a);
 hipError_t launch_pair_mfma(const PairArgs& a);
+// address of this device's static scratch (FCC_NOALLOC_SCRATCH_BYTES bytes), fetched once per device
+hipError_t noalloc_scratch(void** out);
 
 }  // namespace fcc
