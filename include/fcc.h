@@ -35,6 +35,11 @@
  * - TDoA sign: TDoA_ij = t_i - t_j in samples.  If x_j[n] = x_i[n - d] then
  *   the result for pair (i, j) is -d (R = X_i X_j^* of eq. 1 and the
  *   exp(+j 2 pi f tau / N) kernel of eq. 2).
+ * - Failure injection for tests (environment variable FCC_FAULT, read at
+ *   every call): "launch" makes every call that would enqueue a kernel or a
+ *   copy return FCC_ERR_HIP after its argument checks and before anything is
+ *   enqueued; "alloc" makes the host allocations of fcc_plan_create and
+ *   fcc_batch_create fail with FCC_ERR_INTERNAL.
  */
 #ifndef FCC_H_
 #define FCC_H_
@@ -71,6 +76,23 @@ typedef enum {
   FCC_METHOD_GCC = 1              /* eq. (2) evaluated at the I lags (Sec. 3) */
 } fcc_method;
 
+/* Operand types of the projection's matrix-core tiles (eq. 9) for the 16-bit
+ * and 8-bit storage types; FP32 accumulation either way.
+ *   FCC_OPERANDS_FP16     spectra of every storage type widened to FP16
+ *                         (exact for unit-modulus values), FP16 basis rows,
+ *                         products p_k e_i in FP16 (the default);
+ *   FCC_OPERANDS_STORAGE  operands in the storage type: BF16 spectra with BF16
+ *                         basis rows and BF16 products (bf16 tiles); e4m3
+ *                         spectra with e4m3 products p_k e_i, the basis rows
+ *                         scaled per component by a power of two and the
+ *                         dictionary by its inverse (fp8 tiles).  FP16
+ *                         storage has no other type; FP32 plans ignore it.
+ * Batches (fcc_batch_*) use FP16 operands. */
+typedef enum {
+  FCC_OPERANDS_FP16 = 0,
+  FCC_OPERANDS_STORAGE = 1
+} fcc_operands;
+
 /* Problem statement of Sec. 2.  mic_xyz is copied by fcc_plan_create. */
 typedef struct {
   int32_t num_mics;               /* M >= 2                                   */
@@ -85,6 +107,7 @@ typedef struct {
   float alpha;                    /* eq. (1) smoothing, (0, 1]; 1 = none      */
   fcc_precision precision;
   fcc_method method;
+  fcc_operands operands;          /* matrix-core operand types (above)        */
 } fcc_config;
 
 typedef struct fcc_plan_s* fcc_plan;
@@ -107,6 +130,7 @@ typedef struct {
   int32_t spectrum_elem_bytes;    /* 8 (FP32), 4 (BF16/FP16), 2 (FP8)         */
   int32_t interp;                 /* r                                        */
   float alpha;
+  int32_t operands;               /* fcc_operands                             */
 } fcc_plan_info;
 
 /* Validates the configuration and computes, on the host in FP64, everything a

@@ -88,11 +88,15 @@ class Plan:
     Arguments follow the problem statement of the paper (Sec. 2): microphone
     positions (metres), sample rate, speed of sound, frame size N, hop, lag
     range tau_max (0: from the geometry) and rank D (0: full rank).
+    `operands` picks the matrix-core operand types of the 16- and 8-bit
+    storage types: "fp16" (widened, the default) or "storage" (BF16 tiles for
+    bf16 spectra, e4m3 tiles for fp8 spectra).
     """
 
     def __init__(self, mic_xyz, fs: float, c: float = 343.0, frame_size: int = 512,
                  hop: int = 128, tau_max: int = 0, rank: int = 0, interp: int = 1,
-                 alpha: float = 1.0, precision: str = "fp32", method: str = "fcc"):
+                 alpha: float = 1.0, precision: str = "fp32", method: str = "fcc",
+                 operands: str = "fp16"):
         lib = _lib.load()
         self._lib = lib
         xyz = np.ascontiguousarray(np.asarray(mic_xyz, dtype=np.float64).reshape(-1, 3))
@@ -106,10 +110,13 @@ class Plan:
         cfg.frame_size, cfg.hop = int(frame_size), int(hop)
         cfg.tau_max, cfg.rank, cfg.interp = int(tau_max), int(rank), int(interp)
         cfg.alpha = float(alpha)
-        if precision not in PRECISIONS or method not in METHODS:
-            raise ValueError(f"precision in {sorted(PRECISIONS)}, method in {sorted(METHODS)}")
+        if precision not in PRECISIONS or method not in METHODS or operands not in _lib.OPERANDS:
+            raise ValueError(f"precision in {sorted(PRECISIONS)}, method in {sorted(METHODS)}, "
+                             f"operands in {sorted(_lib.OPERANDS)}")
         cfg.precision = PRECISIONS[precision]
         cfg.method = METHODS[method]
+        cfg.operands = _lib.OPERANDS[operands]
+        self.operands = operands
         handle = ctypes.c_void_p()
         _lib.check(lib.fcc_plan_create(ctypes.byref(cfg), ctypes.byref(handle)))
         self._h = handle

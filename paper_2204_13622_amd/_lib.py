@@ -13,6 +13,7 @@ STATUS_NAMES = {0: "FCC_OK", -1: "FCC_ERR_INVALID_ARG", -2: "FCC_ERR_UNSUPPORTED
                 -3: "FCC_ERR_BASIS_AMBIGUOUS", -4: "FCC_ERR_HIP", -5: "FCC_ERR_INTERNAL"}
 PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2, "fp8": 3, "fp8_e4m3": 3}
 METHODS = {"fcc": 0, "gcc": 1}
+OPERANDS = {"fp16": 0, "storage": 1}
 
 # every symbol include/fcc.h declares
 EXPORTS = ("fcc_plan_create", "fcc_plan_destroy", "fcc_plan_query", "fcc_plan_upload",
@@ -39,7 +40,8 @@ class FccConfig(ctypes.Structure):
                 ("frame_size", ctypes.c_int32), ("hop", ctypes.c_int32),
                 ("tau_max", ctypes.c_int32), ("rank", ctypes.c_int32),
                 ("interp", ctypes.c_int32), ("alpha", ctypes.c_float),
-                ("precision", ctypes.c_int32), ("method", ctypes.c_int32)]
+                ("precision", ctypes.c_int32), ("method", ctypes.c_int32),
+                ("operands", ctypes.c_int32)]
 
 
 class FccBatchInfo(ctypes.Structure):
@@ -58,7 +60,8 @@ class FccPlanInfo(ctypes.Structure):
                 ("basis_bytes", ctypes.c_size_t), ("spectrum_bytes_per_frame", ctypes.c_size_t),
                 ("spectrum_elem_bytes", ctypes.c_int32),
                 ("interp", ctypes.c_int32),
-                ("alpha", ctypes.c_float)]
+                ("alpha", ctypes.c_float),
+                ("operands", ctypes.c_int32)]
 
 
 _lib = None

@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfcc.so")
 
-SOURCES = ["fcc_api.cpp", "plan.cpp", "stft_phat.hip", "pair_valu.hip", "pair_mfma.hip", "pair_fold32.hip", "gcc_ifft.hip", "smooth.hip", "doa.hip", "batch.hip", "mlp.hip", "noalloc.hip"]
+SOURCES = ["fcc_api.cpp", "plan.cpp", "stft_phat.hip", "pair_valu.hip", "pair_mfma.hip", "pair_mfma_f16.hip", "pair_mfma_bf16.hip", "pair_mfma_e4m3.hip", "pair_mfma_bf16_native.hip", "pair_mfma_e4m3_native.hip", "pair_fold32.hip", "gcc_ifft.hip", "smooth.hip", "doa.hip", "batch.hip", "mlp.hip", "noalloc.hip"]
 
 ARCH = "gfx950"
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -27,7 +27,7 @@ __global__ __launch_bounds__(stft_core::kThreads) void batch_stft_kernel(
     const BatchArray* __restrict__ arrays, const int32_t* __restrict__ item_array, int64_t first_item,
     const unsigned char* __restrict__ image, const float* __restrict__ audio, unsigned char* __restrict__ spec_base) {
   using Sh = stft_core::StftShape<N>;
-  __shared__ float2 tw[N];
+  __shared__ float2 tw[Sh::TW];
   __shared__ float2 tw1[Sh::T1];
   __shared__ float2 tw2[Sh::T2];
   __shared__ float2 data[Sh::FPB * Sh::NHP];
@@ -103,7 +103,7 @@ __global__ __launch_bounds__(64 * kWaves, 2) void batch_pair_kernel(
     if (a < 0) break;                                  // the same for every thread of the block
     const BatchArray& d = arrays[a];
     const int NH = d.N / 2;
-    pair_core::stage_tables<KB, TT>(lds_all, NH, d.P,
+    pair_core::stage_tables<KB, TT>(lds_all, NH, d.P, d.I,
                                     reinterpret_cast<const uint32_t*>(image + d.img_off + d.tab_prow16),
                                     reinterpret_cast<const float*>(image + d.img_off + d.tab_gexp),
                                     image + d.img_off + d.tab_pairs, 64 * kWaves);
@@ -182,7 +182,7 @@ hipError_t launch_pair_kb(const BatchRun& r, const BatchClass& c, const PairTuni
 int batch_head_words(int Dpad, int NH, int TT, int P) { return pair_core::head_words(Dpad, NH, TT, P); }
 int batch_slab_words(int N, int I) {
   const int spec_words = 16 * (N / 2 + 4);
-  const int y_words = (I + 1) * pair_core::kYStride;
+  const int y_words = pair_core::lag_words(I, I <= 16 ? 1 : (I <= 32 ? 2 : 3));
   return spec_words > y_words ? spec_words : y_words;
 }
 

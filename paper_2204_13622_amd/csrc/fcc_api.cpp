@@ -3,6 +3,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <cstdint>
+#include <cstdlib>
 #include <cstring>
 #include <algorithm>
 #include <tuple>
@@ -53,6 +54,24 @@ fcc_status hip_status(hipError_t e, const char* what) {
   return set_error(FCC_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// Test hook (environment variable FCC_FAULT, read at every call):
+//   launch  every device launch or copy fails with FCC_ERR_HIP on the host,
+//           before anything is enqueued;
+//   alloc   the host allocations of plans and batches fail (FCC_ERR_INTERNAL).
+enum class Fault { kNone, kLaunch, kAlloc };
+Fault fault_mode() {
+  const char* v = std::getenv("FCC_FAULT");
+  if (!v) return Fault::kNone;
+  if (std::strcmp(v, "launch") == 0) return Fault::kLaunch;
+  if (std::strcmp(v, "alloc") == 0) return Fault::kAlloc;
+  return Fault::kNone;
+}
+fcc_status injected_launch_fault(const char* what) {
+  if (fault_mode() != Fault::kLaunch) return FCC_OK;
+  return set_error(FCC_ERR_HIP, std::string(what) + ": injected launch failure (FCC_FAULT=launch)");
+}
+bool injected_alloc_fault() { return fault_mode() == Fault::kAlloc; }
+
 bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
 int64_t frames_of(const fcc::Plan& p, int64_t L) {
@@ -98,6 +117,9 @@ fcc::PairArgs pair_args(const fcc::Plan& p, const void* d_basis, const void* d_s
   a.prow16 = image_ptr(d_basis, p.layout.prow16);
   a.prow32 = reinterpret_cast<const float2*>(image_ptr(d_basis, p.layout.prow32));
   a.gexp = reinterpret_cast<const float*>(image_ptr(d_basis, p.layout.gexp));
+  a.operands = p.operands;
+  a.prow_op = image_ptr(d_basis, p.layout.prow_op);
+  a.gexp_op = reinterpret_cast<const float*>(image_ptr(d_basis, p.layout.gexp_op));
   a.Dfold = p.Dfold;
   a.pfold = reinterpret_cast<const float*>(image_ptr(d_basis, p.layout.pfold));
   a.twiddle_r = reinterpret_cast<const float2*>(image_ptr(d_basis, p.layout.twiddle_r));
@@ -119,6 +141,7 @@ fcc_status run_spectra(const fcc::Plan& p, const void* d_basis, const float* d_x
   a.out = d_spec;
   a.raw = p.alpha < 1.0f;                    // smoothing needs X itself; PHAT comes per pair
   a.stream = stream;
+  if (fcc_status f = injected_launch_fault("stft_phat launch")) return f;
   return hip_status(fcc::launch_stft_phat(a), "stft_phat launch");
 }
 
@@ -159,7 +182,7 @@ extern "C" {
 fcc_status fcc_plan_create(const fcc_config* config, fcc_plan* out) {
   if (!config || !out) return set_error(FCC_ERR_INVALID_ARG, "NULL argument");
   *out = nullptr;
-  fcc_plan_s* h = new (std::nothrow) fcc_plan_s;
+  fcc_plan_s* h = injected_alloc_fault() ? nullptr : new (std::nothrow) fcc_plan_s;
   if (!h) return set_error(FCC_ERR_INTERNAL, "out of host memory");
   std::string err;
   fcc_status st;
@@ -199,6 +222,7 @@ fcc_status fcc_plan_query(fcc_plan plan, fcc_plan_info* info) {
   info->spectrum_elem_bytes = p.spec_elem;
   info->interp = p.r;
   info->alpha = p.alpha;
+  info->operands = p.operands;
   return FCC_OK;
 }
 
@@ -207,6 +231,7 @@ fcc_status fcc_plan_upload(fcc_plan plan, void* d_basis, hipStream_t stream) {
   fcc_status st = check_basis(d_basis);
   if (st != FCC_OK) return st;
   const fcc::Plan& p = plan->p;
+  if (fcc_status f = injected_launch_fault("plan upload")) return f;
   return hip_status(hipMemcpyAsync(d_basis, p.image.data(), p.image.size(), hipMemcpyHostToDevice, stream),
                     "plan upload");
 }
@@ -258,6 +283,7 @@ static fcc_status pair_stage(const fcc::Plan& p, const void* d_basis, const void
   a.y = d_y;
   a.coef = d_coef;
   a.tau_frac = d_tau;
+  if (fcc_status f = injected_launch_fault("pair kernel launch")) return f;
   hipError_t e;
   if (d_coef || d_tau) {
     if (p.method != FCC_METHOD_FCC) return set_error(FCC_ERR_UNSUPPORTED, "coefficients and interpolation need the FCC method");
@@ -313,6 +339,7 @@ static fcc_status smooth_stage(const fcc::Plan& p, const void* d_basis, const vo
   a.stream = stream;
   if (!fcc::smooth_supported(a))
     return set_error(FCC_ERR_UNSUPPORTED, "shape outside the smoothing kernel's limits (rank <= 32, I <= 80)");
+  if (fcc_status f = injected_launch_fault("smoothing kernels launch")) return f;
   return hip_status(fcc::launch_smooth(a), "smoothing kernels launch");
 }
 
@@ -362,6 +389,7 @@ fcc_status fcc_tdoa(fcc_plan plan, const void* d_basis, const float* d_x, int64_
     const TdoaWorkspace w = tdoa_workspace(p, T);
     char* ws = static_cast<char*>(d_workspace);
     float* state = reinterpret_cast<float*>(ws + w.state);
+    if (fcc_status f = injected_launch_fault("fill launch")) return f;
     if ((st = hip_status(fcc::launch_fill_zero(state, 2 * int64_t(p.P) * p.F, stream), "fill launch")) != FCC_OK)
       return st;
     return smooth_stage(p, d_basis, d_workspace, T, state, d_tdoa, nullptr, nullptr, ws + w.scratch, stream);
@@ -385,6 +413,7 @@ fcc_status fcc_tdoa_noalloc(fcc_plan plan, const void* d_basis, const float* d_x
   const size_t frame_bytes = size_t(p.M) * (p.N / 2) * p.spec_elem;
   if (frame_bytes > size_t(FCC_NOALLOC_SCRATCH_BYTES))
     return set_error(FCC_ERR_UNSUPPORTED, "one frame of spectra exceeds FCC_NOALLOC_SCRATCH_BYTES");
+  if (fcc_status f = injected_launch_fault("noalloc launch")) return f;
   void* scratch = nullptr;
   if ((st = hip_status(fcc::noalloc_scratch(&scratch), "static scratch address")) != FCC_OK) return st;
   const int64_t chunk = int64_t(size_t(FCC_NOALLOC_SCRATCH_BYTES) / frame_bytes);
@@ -449,6 +478,7 @@ fcc_status fcc_mlp_forward(const float* d_params, int32_t in_dim, int32_t hidden
   if (st != FCC_OK) return st;
   if (rows == 0) return FCC_OK;
   if (!d_params || !d_coef || !d_out || !d_workspace) return set_error(FCC_ERR_INVALID_ARG, "NULL pointer");
+if (fcc_status f = injected_launch_fault("mlp forward launch")) return f;
   if (fcc::mlp_fused_supported(in_dim, hidden))
     return hip_status(fcc::mlp_infer(d_params, in_dim, hidden, d_coef, rows, d_out, stream), "fused mlp launch");
   return hip_status(fcc::mlp_forward(d_params, in_dim, hidden, d_coef, rows, d_out, d_workspace, stream),
@@ -463,6 +493,7 @@ fcc_status fcc_mlp_backward(const float* d_params, int32_t in_dim, int32_t hidde
   if (rows == 0) return FCC_OK;
   if (!d_params || !d_coef || !d_target || !d_grad || !d_loss_sum || !d_out || !d_workspace)
     return set_error(FCC_ERR_INVALID_ARG, "NULL pointer");
+if (fcc_status f = injected_launch_fault("mlp backward launch")) return f;
   return hip_status(fcc::mlp_backward(d_params, in_dim, hidden, d_coef, d_target, rows, d_grad, d_loss_sum,
                                       d_out, d_workspace, stream),
                     "mlp backward launch");
@@ -473,6 +504,7 @@ fcc_status fcc_mlp_adam(float* d_params, float* d_m, float* d_v, const float* d_
   if (n < 0 || step < 1) return set_error(FCC_ERR_INVALID_ARG, "n must be >= 0 and step >= 1");
   if (n == 0) return FCC_OK;
   if (!d_params || !d_m || !d_v || !d_grad) return set_error(FCC_ERR_INVALID_ARG, "NULL pointer");
+if (fcc_status f = injected_launch_fault("adam launch")) return f;
   return hip_status(fcc::mlp_adam(d_params, d_m, d_v, d_grad, n, lr, beta1, beta2, eps, step, stream),
                     "adam launch");
 }
@@ -581,6 +613,7 @@ fcc_status fcc_doa(fcc_plan plan, const float* d_y, int64_t num_frames, const fl
   a.score = d_score;
   a.stream = stream;
   if (!fcc::doa_supported(a)) return set_error(FCC_ERR_UNSUPPORTED, "one frame's correlations exceed 48 KB");
+  if (fcc_status f = injected_launch_fault("doa launch")) return f;
   return hip_status(fcc::launch_doa(a), "doa launch");
 }
 
@@ -641,7 +674,7 @@ fcc_status fcc_batch_create(const fcc_plan* plans, int32_t num_arrays, const int
   if (!plans || !num_samples || !out || num_arrays < 1)
     return set_error(FCC_ERR_INVALID_ARG, "plans, num_samples and out must be non-NULL, num_arrays >= 1");
   *out = nullptr;
-  fcc_batch b = new (std::nothrow) fcc_batch_s;
+  fcc_batch b = injected_alloc_fault() ? nullptr : new (std::nothrow) fcc_batch_s;
   if (!b) return set_error(FCC_ERR_INTERNAL, "out of host memory");
   auto fail = [&](fcc_status st, const char* msg) {
     delete b;
@@ -674,6 +707,7 @@ fcc_status fcc_batch_create(const fcc_plan* plans, int32_t num_arrays, const int
     d.lag0 = p.r * p.tau_max;
     d.L = num_samples[a];
     d.T = frames_of(p, num_samples[a]);
+    if (d.T * int64_t(p.M) > int64_t(INT32_MAX)) return fail(FCC_ERR_UNSUPPORTED, "too many frames in one array");
     d.audio_off = b->audio_floats;
     d.spec_off = int64_t(spec);
     d.tdoa_off = b->tdoa_count;
@@ -787,6 +821,7 @@ fcc_status fcc_batch_layout(fcc_batch b, int64_t* audio_offset, int64_t* tdoa_of
 fcc_status fcc_batch_upload(fcc_batch b, void* d_image, hipStream_t stream) {
   if (!b || !d_image) return set_error(FCC_ERR_INVALID_ARG, "NULL argument");
   if (!aligned(d_image, 256)) return set_error(FCC_ERR_INVALID_ARG, "d_image must be 256-byte aligned");
+  if (fcc_status f = injected_launch_fault("batch upload")) return f;
   return hip_status(hipMemcpyAsync(d_image, b->image.data(), b->image.size(), hipMemcpyHostToDevice, stream),
                     "batch image copy");
 }
@@ -796,6 +831,7 @@ fcc_status fcc_batch_tdoa(fcc_batch b, const void* d_image, const float* d_audio
   fcc_status st = batch_check(b, d_image, d_audio, d_tdoa, d_workspace);
   if (st != FCC_OK) return st;
   if (b->tdoa_count == 0) return FCC_OK;          // no array holds a whole frame: nothing to launch
+  if (fcc_status f = injected_launch_fault("batch launch")) return f;
   if (!use_graph)
     return hip_status(batch_enqueue(b, batch_run(b, d_image, d_audio, d_tdoa, d_workspace, stream)), "batch launch");
   const void* key[4] = {d_image, d_audio, d_tdoa, d_workspace};
@@ -830,6 +866,7 @@ fcc_status fcc_batch_tune(fcc_batch b, const void* d_image, const float* d_audio
   fcc_status st = batch_check(b, d_image, d_audio, d_tdoa, d_workspace);
   if (st != FCC_OK) return st;
   if (b->tdoa_count == 0) return FCC_OK;          // nothing to time: the default shapes stay
+  if (fcc_status f = injected_launch_fault("batch tuning launch")) return f;
   batch_drop_graph(b);
   const fcc::BatchRun r = batch_run(b, d_image, d_audio, d_tdoa, d_workspace, stream);
   hipEvent_t e0, e1;
@@ -893,7 +930,9 @@ fcc_status fcc_batch_tuning(fcc_batch b, int32_t* values, int32_t capacity) {
 }
 
 const char* fcc_status_string(fcc_status status) {
-  switch (status) {
+  int32_t v;                          // the int a C caller passed, whatever its value
+  std::memcpy(&v, &status, sizeof v);
+  switch (v) {
     case FCC_OK: return "FCC_OK";
     case FCC_ERR_INVALID_ARG: return "FCC_ERR_INVALID_ARG";
     case FCC_ERR_UNSUPPORTED: return "FCC_ERR_UNSUPPORTED";

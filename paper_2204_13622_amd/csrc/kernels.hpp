@@ -129,6 +129,10 @@ struct PairArgs {
   const void* prow16;        // half2  [Dpad][N/2] full-length rows, slot pairs
   const float2* prow32;      // float2 [Dpad][N/2]
   const float* gexp;         // [Ipad][Dpad] G = Dc - Ds
+  fcc_operands operands;     // matrix-core operand types
+  const void* prow_op;       // [Dpad][N/2] rows in the storage type's operand form (BF16 pairs, or
+                             // FP16 pairs scaled by 2^e_k for e4m3), or null
+  const float* gexp_op;      // [Ipad][Dpad] G with the rows' inverse scales, or null
   int Dfold;                 // D padded to the FP32 fold kernel's register block
   const float* pfold;        // [N/4 + 1][Dfold] p_hat transposed, zero beyond D
   const float2* twiddle_r;   // [r N] exp(-j 2 pi n / (r N))

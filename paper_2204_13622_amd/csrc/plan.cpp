@@ -214,7 +214,24 @@ fcc_status fail(std::string& err, fcc_status st, const std::string& msg) {
 
 }  // namespace
 
+// An enum field of the C configuration as the integer the caller stored: a C
+// caller may store any int there, and reading it as the C++ enum type would
+// be undefined outside the enumerators' range.
+static int32_t enum_bits(const void* field) {
+  int32_t v;
+  std::memcpy(&v, field, sizeof v);
+  return v;
+}
+
 fcc_status build_plan(const fcc_config& cfg, Plan& pl, std::string& err) {
+  static_assert(sizeof(fcc_precision) == 4 && sizeof(fcc_method) == 4 && sizeof(fcc_operands) == 4,
+                "C enums are int-sized");
+  const int32_t precision = enum_bits(&cfg.precision), method = enum_bits(&cfg.method),
+                operands = enum_bits(&cfg.operands);
+  if (precision < FCC_FP32 || precision > FCC_FP8_E4M3) return fail(err, FCC_ERR_INVALID_ARG, "unknown precision");
+  if (method != FCC_METHOD_FCC && method != FCC_METHOD_GCC) return fail(err, FCC_ERR_INVALID_ARG, "unknown method");
+  if (operands != FCC_OPERANDS_FP16 && operands != FCC_OPERANDS_STORAGE)
+    return fail(err, FCC_ERR_INVALID_ARG, "unknown operand type");
   if (cfg.num_mics < 2) return fail(err, FCC_ERR_INVALID_ARG, "num_mics must be >= 2");
   if (cfg.num_mics > 32) return fail(err, FCC_ERR_UNSUPPORTED, "num_mics > 32 is not built");
   if (!cfg.mic_xyz) return fail(err, FCC_ERR_INVALID_ARG, "mic_xyz is NULL");
@@ -232,10 +249,6 @@ fcc_status build_plan(const fcc_config& cfg, Plan& pl, std::string& err) {
     return fail(err, FCC_ERR_UNSUPPORTED, "alpha < 1 is built for FP32 spectra only");
   if (cfg.alpha < 1.0f && cfg.method != FCC_METHOD_FCC)
     return fail(err, FCC_ERR_UNSUPPORTED, "alpha < 1 is built for the FCC method only");
-  if (cfg.precision < FCC_FP32 || cfg.precision > FCC_FP8_E4M3)
-    return fail(err, FCC_ERR_INVALID_ARG, "unknown precision");
-  if (cfg.method != FCC_METHOD_FCC && cfg.method != FCC_METHOD_GCC)
-    return fail(err, FCC_ERR_INVALID_ARG, "unknown method");
   if (cfg.tau_max < 0) return fail(err, FCC_ERR_INVALID_ARG, "tau_max must be >= 0");
   if (cfg.rank < 0) return fail(err, FCC_ERR_INVALID_ARG, "rank must be >= 0");
 
@@ -251,6 +264,7 @@ fcc_status build_plan(const fcc_config& cfg, Plan& pl, std::string& err) {
   pl.alpha = cfg.alpha;
   pl.precision = cfg.precision;
   pl.method = cfg.method;
+  pl.operands = cfg.operands;
   pl.xyz.assign(cfg.mic_xyz, cfg.mic_xyz + 3 * size_t(pl.M));
   for (double v : pl.xyz)
     if (!std::isfinite(v)) return fail(err, FCC_ERR_INVALID_ARG, "mic_xyz has a non-finite entry");
@@ -358,6 +372,8 @@ fcc_status build_plan(const fcc_config& cfg, Plan& pl, std::string& err) {
   L.prow32 = off;  off = align256(off + 2 * sizeof(float) * size_t(pl.Dpad) * NH);
   L.prow16 = off;  off = align256(off + 2 * sizeof(uint16_t) * size_t(pl.Dpad) * NH);
   L.gexp = off;    off = align256(off + sizeof(float) * size_t(pl.Ipad) * pl.Dpad);
+  L.prow_op = off; off = align256(off + 2 * sizeof(uint16_t) * size_t(pl.Dpad) * NH);
+  L.gexp_op = off; off = align256(off + sizeof(float) * size_t(pl.Ipad) * pl.Dpad);
   pl.Dfold = 0;
   for (int c : {4, 8, 12, 16, 24, 32, 48, 64})
     if (D <= c) { pl.Dfold = c; break; }
@@ -414,6 +430,35 @@ fcc_status build_plan(const fcc_config& cfg, Plan& pl, std::string& err) {
   for (int i = 0; i < I; ++i)
     for (int k = 0; k < D; ++k)
       fput(L.gexp, size_t(i) * pl.Dpad + k, pl.dc[size_t(i) * D + k] - pl.ds[size_t(i) * D + k]);
+  // operands in the storage type: BF16 rows as they are; e4m3 products need
+  // the rows scaled into e4m3's range, by a power of two per component
+  // (exact), which the dictionary takes back
+  for (int k = 0; k < D; ++k) {
+    double pmax = 0.0;
+    for (int f = 0; f <= m; ++f) pmax = std::max(pmax, std::fabs(pl.p_hat[size_t(k) * (m + 1) + f]));
+    int e = 0;
+    if (pl.precision == FCC_FP8_E4M3 && pmax > 0.0) {
+      e = int(std::floor(std::log2(240.0 / pmax)));
+      while (std::ldexp(pmax, e) > 240.0) --e;
+      while (std::ldexp(pmax, e + 1) <= 240.0) ++e;
+    }
+    for (int f = 0; f < NH; ++f) {
+      const double lo = std::ldexp(prow(k, f), e), hi = std::ldexp((f == 0) ? prow(k, NH) : prow(k, f), e);
+      uint16_t wlo, whi;
+      if (pl.precision == FCC_BF16) {
+        wlo = to_bf16(float(lo));
+        whi = to_bf16(float(hi));
+      } else {
+        wlo = to_fp16(float(lo));
+        whi = to_fp16(float(hi));
+      }
+      std::memcpy(img + L.prow_op + 4 * (size_t(k) * NH + f), &wlo, 2);
+      std::memcpy(img + L.prow_op + 4 * (size_t(k) * NH + f) + 2, &whi, 2);
+    }
+    for (int i = 0; i < I; ++i)
+      fput(L.gexp_op, size_t(i) * pl.Dpad + k,
+           std::ldexp(pl.dc[size_t(i) * D + k] - pl.ds[size_t(i) * D + k], -e));
+  }
   for (int k = 0; k < D && k < pl.Dfold; ++k)      // transposed: row f holds p_hat_k(f) for all k
     for (int f = 0; f <= m; ++f) fput(L.pfold, size_t(f) * pl.Dfold + k, pl.p_hat[size_t(k) * (m + 1) + f]);
   for (int i = 0; i < I; ++i) {

@@ -25,6 +25,11 @@ struct ImageLayout {
   size_t prow32 = 0;      // float2 [Dpad][N/2]
   size_t prow16 = 0;      // half2  [Dpad][N/2]
   size_t gexp = 0;        // float [Ipad][Dpad]  G(tau_i, k) = Dc - Ds; zero padded
+  // operands in the storage type: BF16 pairs (bf16 plans) or FP16 pairs of
+  // 2^e_k p_k (e4m3 plans, e_k putting max |2^e_k p_k| in (120, 240]), and G
+  // with column k divided by 2^e_k
+  size_t prow_op = 0;     // [Dpad][N/2] 4 bytes per slot
+  size_t gexp_op = 0;     // float [Ipad][Dpad]
   size_t pfold = 0;       // float [N/4 + 1][Dfold] p_hat, transposed, for the FP32 fold kernel
   size_t total = 0;
 };
@@ -37,6 +42,7 @@ struct Plan {
   float alpha = 1.0f;
   fcc_precision precision = FCC_FP32;
   fcc_method method = FCC_METHOD_FCC;
+  fcc_operands operands = FCC_OPERANDS_FP16;
   std::vector<double> xyz;          // [M][3]
 
   // FP64 basis in component order S, A, S, A, ... (eq. 6)

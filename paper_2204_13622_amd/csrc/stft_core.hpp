@@ -35,16 +35,21 @@ struct StftShape {
   static constexpr int P1 = RD::R0, P2 = RD::R0 * RD::R1;
   static constexpr int T1 = RD::R1 > 1 ? RD::R1 * P1 : 1; // twiddle table sizes of the LDS passes
   static constexpr int T2 = RD::R2 > 1 ? RD::R2 * P2 : 1;
-  static constexpr int lds_float2 = N + T1 + T2 + FPB * NHP;
+  // front table: NH window pairs (w(2n), w(2n + 1)), then W^f for f = 0 .. NH / 2
+  static constexpr int TW = NH + NH / 2 + 1;
+  static constexpr int lds_float2 = TW + T1 + T2 + FPB * NHP;
 };
 
-// Block-wide: the full-circle twiddles (and, through their cosines, the
-// window) and the per-pass twiddle tables into LDS.
+// Block-wide: the periodic Hann window and the split twiddles (from the
+// full-circle FP64-computed twiddles) and the per-pass twiddle tables into LDS.
 template <int N>
 __device__ __forceinline__ void load_tables(float2* tw, float2* tw1, float2* tw2, const float2* __restrict__ twiddle) {
   using Sh = StftShape<N>;
   using RD = typename Sh::RD;
-  for (int f = threadIdx.x; f < N; f += kThreads) tw[f] = twiddle[f];
+  constexpr int NH = Sh::NH;
+  for (int n = threadIdx.x; n < NH; n += kThreads)      // w[n] = 0.5 - 0.5 cos(2 pi n / N)
+    tw[n] = make_float2(0.5f - 0.5f * twiddle[2 * n].x, 0.5f - 0.5f * twiddle[2 * n + 1].x);
+  for (int f = threadIdx.x; f <= NH / 2; f += kThreads) tw[NH + f] = twiddle[f];
   if constexpr (RD::R1 > 1)
     for (int e = threadIdx.x; e < Sh::T1; e += kThreads) {
       const int r = e / Sh::P1, k = e % Sh::P1;
@@ -57,39 +62,64 @@ __device__ __forceinline__ void load_tables(float2* tw, float2* tw1, float2* tw2
     }
 }
 
+// PHAT scale of one bin from its squared magnitude: 1 / |X|, or 0 below the
+// smallest normal float
+__device__ __forceinline__ float phat_scale(float n2) {
+  const float s = rsqrtf(n2);
+  return n2 < 1.17549435e-38f ? 0.f : s;
+}
+
+// The R0 sample pairs lane lf of transform b needs for the first pass:
+// (x[2n], x[2n + 1]) for n = lf + r NB, unwindowed (b < nfft < 2^31).
+template <int N>
+__device__ __forceinline__ void load_samples(float2 (&u)[StftShape<N>::RD::R0], const float* __restrict__ x,
+                                             int64_t ld, int M, int hop, uint32_t b, int lf) {
+  using RD = typename StftShape<N>::RD;
+  constexpr int R = RD::R0, NB = StftShape<N>::NH / R;
+  const uint32_t t = b / (uint32_t)M;
+  const int mic = (int)(b - t * (uint32_t)M);
+  const float* src = x + (int64_t)mic * ld + (int64_t)t * hop;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int n = lf + r * NB;
+    u[r] = make_float2(src[2 * n], src[2 * n + 1]);
+  }
+}
+
 // Block-wide: the FPB transforms lblk * FPB .. + FPB - 1 (transform b is
-// microphone b % M of frame b / M; those at or past nfft idle).  Tables in
-// LDS already; `data` is the block's transform scratch.
-template <int N, class S, bool RAW>
-__device__ __forceinline__ void transforms(const float2* tw, const float2* tw1, const float2* tw2, float2* data,
-                                           const float* __restrict__ x, int64_t ld, int M, int hop, int64_t nfft,
-                                           typename S::T* __restrict__ out, int64_t lblk) {
+// microphone b % M of frame b / M; those at or past nfft idle; nfft < 2^31),
+// given the first pass's samples of this lane's transform in `u` (loaded by
+// load_samples; ignored where inactive).  Tables in LDS already; `data` is
+// the block's transform scratch.  `between` runs after the first pass has
+// stored its outputs (a persistent caller issues its next loads there).
+template <int N, class S, bool RAW, class Between>
+__device__ __forceinline__ void transform_samples(const float2* tw, const float2* tw1, const float2* tw2,
+                                                  float2* data, float2 (&u)[StftShape<N>::RD::R0], int64_t nfft,
+                                                  typename S::T* __restrict__ out, int64_t lblk,
+                                                  Between&& between) {
   using Sh = StftShape<N>;
   using RD = typename Sh::RD;
   constexpr int NH = Sh::NH, LF = Sh::LF, FPB = Sh::FPB, NHP = Sh::NHP, P1 = Sh::P1, P2 = Sh::P2;
   const int slot = threadIdx.x / LF, lf = threadIdx.x % LF;
-  const int64_t b = lblk * FPB + slot;   // = t * M + m
-  const bool active = b < nfft;
+  const uint32_t b = (uint32_t)lblk * FPB + slot;   // = t * M + m
+  const bool active = b < (uint64_t)nfft;
   float2* buf = data + slot * NHP;
-  // first pass straight from memory: radix R0, no twiddles (p = 1)
+  const float2* win = tw;                          // window pairs
+  const float2* wsp = tw + NH;                     // W^f, f = 0 .. NH / 2
+  // first pass: radix R0 on the windowed samples, no twiddles (p = 1)
   {
     constexpr int R = RD::R0, NB = NH / R;
-    float2 u[R];
     if (active) {
-      const int mic = (int)(b % M);
-      const int64_t t = b / M;
-      const float* src = x + (int64_t)mic * ld + t * hop;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const int n = lf + r * NB;
-        const float w0 = 0.5f - 0.5f * tw[2 * n].x;          // periodic Hann
-        const float w1 = 0.5f - 0.5f * tw[2 * n + 1].x;
-        u[r] = make_float2(w0 * src[2 * n], w1 * src[2 * n + 1]);
+        const float2 w = win[lf + r * NB];         // periodic Hann at 2n, 2n + 1
+        u[r] = make_float2(w.x * u[r].x, w.y * u[r].y);
       }
       Dft<R>::run(u);
 #pragma unroll
       for (int r = 0; r < R; ++r) buf[pidx(lf * R + r)] = u[r];
     }
+    between();
     __syncthreads();
   }
   if constexpr (RD::R1 > 1) lds_pass<RD::R1, P1, NH, LF>(buf, tw1, lf, active);
@@ -100,33 +130,56 @@ __device__ __forceinline__ void transforms(const float2* tw, const float2* tw1, 
   // X(f) = E + W^f O and X(NH - f) = conj(E - W^f O).  PHAT is blind to a
   // common factor, so the halves are dropped unless the raw X is wanted.
   // Lane lf takes f = lf, lf + LF, ... < NH / 2 (the same number of bins on
-  // every lane); f = 0 is the DC / Nyquist slot, and its lane also takes the
-  // centre bin NH / 2, which is its own mirror.
+  // every lane); f = 0 is the DC / Nyquist slot, done after the loop by the
+  // lanes with lf = 0, which also take the centre bin NH / 2 (its own mirror).
   constexpr float h = RAW ? 0.5f : 1.f;
-  typename S::T* dst = out + b * NH;
-  for (int f = lf; f < NH / 2; f += LF) {
-    if (f == 0) {
-      // X(0) = Re Z(0) + Im Z(0), X(N/2) = Re Z(0) - Im Z(0); both real
-      const float2 z0 = buf[0];
-      if (RAW) dst[0] = spec_encode<S>(make_float2(z0.x + z0.y, z0.x - z0.y));
-      else dst[0] = spec_encode<S>(make_float2(phat_real(z0.x + z0.y), phat_real(z0.x - z0.y)));
-      // centre: E = Re Z(NH/2), O = Im Z(NH/2), X = E + W^(NH/2) O
-      const float2 zc = buf[pidx(NH / 2)];
-      const float2 wc = tw[NH / 2];
-      const float2 Xc = make_float2(zc.x + wc.x * zc.y, wc.y * zc.y);
-      dst[NH / 2] = spec_encode<S>(RAW ? Xc : phat_complex(Xc));
-      continue;
-    }
+  typename S::T* dst = out + (int64_t)b * NH;
+  constexpr int kIters = (NH / 2 + LF - 1) / LF;
+#pragma unroll
+  for (int k = 0; k < kIters; ++k) {
+    const int f = lf + k * LF;
+    if (f == 0 || f >= NH / 2) continue;
     const float2 zf = buf[pidx(f)];
     const float2 zr = buf[pidx(NH - f)];
     const float2 e = make_float2(h * (zf.x + zr.x), h * (zf.y - zr.y));
     const float2 o = make_float2(h * (zf.y + zr.y), -h * (zf.x - zr.x));
-    const float2 wo = cmul(tw[f], o);
+    const float2 wo = cmul(wsp[f], o);
     const float2 Xa = cadd(e, wo);
     const float2 Xb = make_float2(e.x - wo.x, wo.y - e.y);
-    dst[f] = spec_encode<S>(RAW ? Xa : phat_complex(Xa));
-    dst[NH - f] = spec_encode<S>(RAW ? Xb : phat_complex(Xb));
+    if (RAW) {
+      dst[f] = spec_encode<S>(Xa);
+      dst[NH - f] = spec_encode<S>(Xb);
+    } else {
+      const float sa = phat_scale(Xa.x * Xa.x + Xa.y * Xa.y);
+      const float sb = phat_scale(Xb.x * Xb.x + Xb.y * Xb.y);
+      dst[f] = spec_encode<S>(make_float2(Xa.x * sa, Xa.y * sa));
+      dst[NH - f] = spec_encode<S>(make_float2(Xb.x * sb, Xb.y * sb));
+    }
   }
+  if (lf == 0) {
+    // X(0) = Re Z(0) + Im Z(0), X(N/2) = Re Z(0) - Im Z(0); both real
+    const float2 z0 = buf[0];
+    if (RAW) dst[0] = spec_encode<S>(make_float2(z0.x + z0.y, z0.x - z0.y));
+    else dst[0] = spec_encode<S>(make_float2(phat_real(z0.x + z0.y), phat_real(z0.x - z0.y)));
+    // centre: E = Re Z(NH/2), O = Im Z(NH/2), X = E + W^(NH/2) O
+    const float2 zc = buf[pidx(NH / 2)];
+    const float2 wc = wsp[NH / 2];
+    const float2 Xc = make_float2(zc.x + wc.x * zc.y, wc.y * zc.y);
+    dst[NH / 2] = spec_encode<S>(RAW ? Xc : phat_complex(Xc));
+  }
+}
+
+// Block-wide: the FPB transforms lblk * FPB .. + FPB - 1, samples loaded here.
+template <int N, class S, bool RAW>
+__device__ __forceinline__ void transforms(const float2* tw, const float2* tw1, const float2* tw2, float2* data,
+                                           const float* __restrict__ x, int64_t ld, int M, int hop, int64_t nfft,
+                                           typename S::T* __restrict__ out, int64_t lblk) {
+  using Sh = StftShape<N>;
+  const int slot = threadIdx.x / Sh::LF, lf = threadIdx.x % Sh::LF;
+  const uint32_t b = (uint32_t)lblk * Sh::FPB + slot;
+  float2 u[Sh::RD::R0];
+  if (b < (uint64_t)nfft) load_samples<N>(u, x, ld, M, hop, b, lf);
+  transform_samples<N, S, RAW>(tw, tw1, tw2, data, u, nfft, out, lblk, [] {});
 }
 
 }  // namespace stft_core

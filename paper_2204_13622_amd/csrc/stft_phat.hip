@@ -36,21 +36,40 @@ __global__ __launch_bounds__(kThreads) void stft_phat_kernel(
     const float* __restrict__ x, int64_t ld, int M, int hop, int64_t nfft,
     const float2* __restrict__ twiddle, typename S::T* __restrict__ out) {
   using Sh = StftShape<N>;
-  __shared__ float2 tw[N];
+  __shared__ float2 tw[Sh::TW];
   __shared__ float2 tw1[Sh::T1];
   __shared__ float2 tw2[Sh::T2];
   __shared__ float2 data[Sh::FPB * Sh::NHP];
 
-  // Workgroups are dealt to the 8 XCDs round-robin; give each XCD one
-  // contiguous run of transforms so the 4x overlap of neighbouring frames is
-  // served from that XCD's L2 instead of HBM.
-  const unsigned nblk = gridDim.x;
+  // Persistent workgroups, dealt to the 8 XCDs round-robin: XCD x walks the
+  // x-th contiguous run of the logical blocks (FPB transforms each), its
+  // workgroups side by side, so the 4x overlap of neighbouring frames is
+  // served from that XCD's L2 instead of HBM.  Each lane holds the next
+  // block's samples in registers while the current block is transformed.
+  const int64_t nblk = (nfft + Sh::FPB - 1) / Sh::FPB;
+  const unsigned grid = gridDim.x;
   const unsigned xcd = blockIdx.x % kXcds, local = blockIdx.x / kXcds;
-  const unsigned per = nblk / kXcds, extra = nblk % kXcds;     // blocks per XCD (first `extra` get one more)
-  const unsigned lblk = xcd * per + (xcd < extra ? xcd : extra) + local;
+  const unsigned nx = grid / kXcds + (xcd < grid % kXcds ? 1u : 0u);    // workgroups on this XCD
+  const int64_t per = nblk / kXcds, extra = nblk % kXcds;
+  const int64_t begin = xcd * per + (xcd < extra ? xcd : extra);
+  const int64_t end = begin + per + (xcd < extra ? 1 : 0);
   load_tables<N>(tw, tw1, tw2, twiddle);
   __syncthreads();
-  transforms<N, S, RAW>(tw, tw1, tw2, data, x, ld, M, hop, nfft, out, lblk);
+  const int slot = threadIdx.x / Sh::LF, lf = threadIdx.x % Sh::LF;
+  float2 u[Sh::RD::R0], nxt[Sh::RD::R0];
+  int64_t lblk = begin + local;
+  if (lblk < end && (uint64_t)lblk * Sh::FPB + slot < (uint64_t)nfft)
+    load_samples<N>(nxt, x, ld, M, hop, (uint32_t)(lblk * Sh::FPB + slot), lf);
+  for (; lblk < end; lblk += nx) {
+#pragma unroll
+    for (int r = 0; r < Sh::RD::R0; ++r) u[r] = nxt[r];
+    const int64_t next = lblk + nx;
+    transform_samples<N, S, RAW>(tw, tw1, tw2, data, u, nfft, out, lblk, [&] {
+      if (next < end && (uint64_t)next * Sh::FPB + slot < (uint64_t)nfft)
+        load_samples<N>(nxt, x, ld, M, hop, (uint32_t)(next * Sh::FPB + slot), lf);
+    });
+    __syncthreads();   // the next block's first pass rewrites the scratch
+  }
 }
 
 template <int N, class S, bool RAW>
@@ -58,7 +77,19 @@ hipError_t launch_n(const StftArgs& a) {
   constexpr int FPB = StftShape<N>::FPB;
   const int64_t nfft = a.T * a.M;
   const int64_t blocks = (nfft + FPB - 1) / FPB;
-  hipLaunchKernelGGL((stft_phat_kernel<N, S, RAW>), dim3((unsigned)blocks), dim3(kThreads), 0, a.stream,
+  // persistent grid: as many workgroups as the CUs hold at once (registers
+  // and LDS decide), each walking its XCD's run of blocks
+  int dev = 0, cus = 256, per_cu = 0;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
+  }
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, stft_phat_kernel<N, S, RAW>, kThreads, 0) != hipSuccess ||
+      per_cu < 1)
+    per_cu = 1;
+  const int64_t cap = int64_t(per_cu) * cus;
+  const int64_t grid = blocks < cap ? blocks : cap;
+  hipLaunchKernelGGL((stft_phat_kernel<N, S, RAW>), dim3((unsigned)grid), dim3(kThreads), 0, a.stream,
                      a.x, a.ld, a.M, a.hop, nfft, a.twiddle, static_cast<typename S::T*>(a.out));
   return hipGetLastError();
 }

@@ -87,6 +87,27 @@ def test_spectra_fp32(torch, fcc, config, seconds):
     assert np.abs(np.abs(e_gpu[mag > 0]) - 1).max() < 1e-5
 
 
+@pytest.mark.parametrize("precision", ["fp16", "bf16", "fp8"])
+@pytest.mark.parametrize("config,seconds", [(1, 1.0), (2, 1.0), (3, 0.3)])
+def test_storage_encoding(torch, fcc, precision, config, seconds):
+    """The front end's storage encoders: the whitened spectra in a 16- or
+    8-bit type are the FP32 spectra of the same kernel rounded to nearest
+    even, bit for bit (host rounding by torch)."""
+    _say(f"storage encoding {precision} config {config}")
+    rec = make_recording(config, seconds=seconds)
+    x = _dev(torch, rec.x)
+    ref = _plan(fcc, rec, 0).spectra(x)
+    p = _plan(fcc, rec, 0, precision=precision)
+    got = p.spectra(x)
+    torch.cuda.synchronize()
+    want = ref.cpu().to(p.spectrum_dtype())
+    g = got.cpu().view(torch.uint8 if precision == "fp8" else torch.int16)
+    w = want.view(torch.uint8 if precision == "fp8" else torch.int16)
+    bad = int((g != w).sum())
+    print(f"{precision}: {bad} of {g.numel()} values differ", flush=True)
+    assert bad == 0
+
+
 # ----------------------------------------------------- pair stage (isolated) --
 
 @pytest.mark.parametrize("config,seconds,D", [(1, 1.0, 9), (1, 1.0, 5), (2, 1.0, 6), (2, 1.0, 11),
@@ -238,10 +259,20 @@ def rec2_full():
     return rec, packed
 
 
-@pytest.mark.parametrize("precision,D,min_agree,max_err", [
-    ("fp16", 11, 0.995, 5e-3), ("fp16", 6, 0.995, 5e-3), ("bf16", 11, 0.98, 3e-2), ("bf16", 6, 0.98, 3e-2),
-    ("fp8", 11, 0.90, 0.3), ("fp8", 6, 0.90, 0.3)])
-def test_full_size_headline_16bit(torch, fcc, rec2_full, precision, D, min_agree, max_err):
+# bar on the same operands: an operand type of unit roundoff u rounds each
+# product p_k e_i and each rotated spectrum value by at most u, so a term of
+# the sums errs by at most 2u relative; the FP16 bar (5e-3) is about 5 x 2u,
+# and the BF16 and e4m3 bars keep that multiple
+SAME_OPERANDS_BAR = {"fp16": 5e-3, "bf16": 2e-2, "fp8": 0.64}
+
+
+@pytest.mark.parametrize("precision,D,min_agree,max_err,operands", [
+    ("fp16", 11, 0.995, 5e-3, "fp16"), ("fp16", 6, 0.995, 5e-3, "fp16"),
+    ("bf16", 11, 0.98, 3e-2, "fp16"), ("bf16", 6, 0.98, 3e-2, "fp16"),
+    ("fp8", 11, 0.90, 0.3, "fp16"), ("fp8", 6, 0.90, 0.3, "fp16"),
+    ("bf16", 11, 0.98, 3e-2, "storage"), ("bf16", 6, 0.98, 3e-2, "storage"),
+    ("fp8", 11, 0.85, 0.4, "storage"), ("fp8", 6, 0.85, 0.4, "storage")])
+def test_full_size_headline_16bit(torch, fcc, rec2_full, precision, D, min_agree, max_err, operands):
     """The benchmarked call at full size: fcc_tdoa on 60 s of the benchmark
     workload, T = 7497 frames.  The pair stage's persistent grid holds
     2 x CUs workgroups of 4 wavefronts, so every wavefront walks 3-4 frames
@@ -257,8 +288,9 @@ def test_full_size_headline_16bit(torch, fcc, rec2_full, precision, D, min_agree
     (3) Against the FP64 oracle on the unquantised audio: agreement rate and
         maximum relative correlation error, bounded per storage type."""
     rec, packed = rec2_full
-    _say(f"headline full size: config 2, T=7497, {precision}, D={D}")
-    p = _plan(fcc, rec, D, precision=precision)
+    _say(f"headline full size: config 2, T=7497, {precision}, D={D}, {operands} operands")
+    p = _plan(fcc, rec, D, precision=precision, operands=operands)
+    bar = SAME_OPERANDS_BAR[precision] if operands == "storage" else 5e-3
     T = p.num_frames(rec.L)
     assert T == 7497 and p.P == 120 and p.I == 11
     rng = np.random.default_rng(2200 + D)
@@ -277,10 +309,10 @@ def test_full_size_headline_16bit(torch, fcc, rec2_full, precision, D, min_agree
     y_s, t_s = y.cpu().numpy()[frames], t.cpu().numpy()[frames]
     del y, spec_q
     err = corr_errors(y_s, y_ref)
-    rep = tdoa_report(t_s, y_ref, p.tau_max, 5e-3)
-    print(f"[same operands {precision} D={D}] max rel corr err {err.max():.3e}, "
-          f"agreement {rep['agreement']:.5f} ({rep['qualified']} qualified)", flush=True)
-    assert err.max() < 5e-3
+    rep = tdoa_report(t_s, y_ref, p.tau_max, bar)
+    print(f"[same operands {precision} D={D} {operands}] max rel corr err {err.max():.3e}, "
+          f"mean {err.mean():.3e}, agreement {rep['agreement']:.5f} ({rep['qualified']} qualified)", flush=True)
+    assert err.max() < bar
     assert rep["mismatch_qualified"] == 0, rep
     assert rep["invalid_elsewhere"] == 0, rep
 
@@ -299,8 +331,8 @@ def test_full_size_headline_16bit(torch, fcc, rec2_full, precision, D, min_agree
     del y, spec
     e = corr_errors(y_s, y_ref)
     rep = tdoa_report(t_s, y_ref, p.tau_max, float(e.max()))
-    print(f"[fp64 oracle {precision} D={D}] agreement {rep['agreement']:.5f} max rel err {e.max():.3e} "
-          f"mean {e.mean():.3e}", flush=True)
+    print(f"[fp64 oracle {precision} D={D} {operands}] agreement {rep['agreement']:.5f} max rel err "
+          f"{e.max():.3e} mean {e.mean():.3e}", flush=True)
     assert rep["agreement"] >= min_agree
     assert e.max() <= max_err
     assert rep["mismatch_qualified"] == 0
@@ -485,6 +517,35 @@ def test_mfma_pair_stage_fp16(torch, fcc, config, seconds, D, M):
     # size against a peak of order N keep the relative error near 1e-3
     assert e.max() < 5e-3
     rep = tdoa_report(t, y_ref, p.tau_max, 5e-3)
+    assert rep["mismatch_qualified"] == 0, rep
+    assert rep["invalid_elsewhere"] == 0, rep
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp8"])
+@pytest.mark.parametrize("config,seconds,D,M", [(2, 1.0, 6, None), (2, 1.0, 11, 9), (2, 1.0, 6, 2),
+                                                (3, 0.3, 15, None), (3, 0.3, 29, 7), (1, 1.0, 9, None)])
+def test_native_operand_pair_stage(torch, fcc, precision, config, seconds, D, M):
+    """Matrix-core tiles in the storage type (BF16, or e4m3 with per-component
+    power-of-two scales) against the FP64 oracle on the same rounded spectra;
+    full and partial blocks of four microphones, one to two lag tiles."""
+    _say(f"native operands {precision} config {config} D={D} M={M}")
+    rec = make_recording(config, seconds=seconds, M=M) if M else make_recording(config, seconds=seconds)
+    p = _plan(fcc, rec, D, precision=precision, operands="storage")
+    assert p.info.operands == 1
+    X = O.stft(rec.x, rec.N, rec.hop)
+    B = O.fcc_basis(rec.N, p.tau_max, D)
+    from paper_2204_13622_amd import Plan
+    spec_q, e_q = _quantize(Plan.pack_spectrum(O.phat(X)), precision)
+    e = Plan.unpack_spectrum(e_q)
+    R = np.stack([e[:, i] * np.conj(e[:, j]) for i, j in O.mic_pairs(e.shape[1])], axis=1)
+    y_ref = O.fcc_corr(R, B)
+    y = p.correlation(spec_q).cpu().numpy()
+    t = p.tdoa_from_spectra(spec_q).cpu().numpy()
+    bar = SAME_OPERANDS_BAR[precision]
+    err = corr_errors(y, y_ref)
+    print(f"{precision} operands: max rel corr err {err.max():.3e}, mean {err.mean():.3e}", flush=True)
+    assert err.max() < bar
+    rep = tdoa_report(t, y_ref, p.tau_max, bar)
     assert rep["mismatch_qualified"] == 0, rep
     assert rep["invalid_elsewhere"] == 0, rep
 
