@@ -35,11 +35,12 @@ def parse_args():
     ap.add_argument("--rank", type=int, default=11)
     ap.add_argument("--no-sweep", action="store_true", help="skip the precision/rank/method sweep")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--cpu-workers", type=int, default=0,
+                    help="worker processes of the CPU oracle baseline (0: the available cores, at most 16)")
     ap.add_argument("--seed", type=int, default=2000)
     ap.add_argument("--settle", type=float, default=0.3, metavar="SECONDS",
                     help="untimed steps before any timing so the GPU clocks settle (0 under counter runs)")
-    ap.add_argument("--batch-seconds", type=float, default=2.0,
+    ap.add_argument("--batch-seconds", type=float, default=10.0,
                     help="audio per array in the 256-array batch measurement")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run plain device copies of this many MiB (counter calibration)")
@@ -120,26 +121,82 @@ def traffic_for(kernel_file: str, workload: str, precision: str, rank: int):
     return None
 
 
-def cpu_baseline(rec, tau_max, D, budget_s):
-    import numpy as np
+def busy_for(kernel_file: str, workload: str, precision: str, rank: int):
+    """MFMA busy share of the kernel's SIMD-cycles from the committed counter
+    record, if it still matches the kernel source."""
+    path = os.path.join(ROOT, "profiles", "busy.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    digest = kernel_source_digest(kernel_file)
+    for r in rec.get("records", []):
+        if (digest is not None and r.get("kernel_file") == kernel_file and r.get("source_sha256") == digest
+                and r.get("workload") == workload and r.get("precision") == precision
+                and r.get("rank") == rank):
+            return r.get("mfma_busy")
+    return None
+
+
+def _oracle_frames(job):
+    """One worker's share of the CPU baseline: the FP64 oracle from audio to
+    int32 lags on a run of frames (its audio slice starts at the run's first
+    frame).  One BLAS thread per worker process."""
+    x, N, hop, tau_max, B = job
     from threadpoolctl import threadpool_limits
+    import oracle.fcc_oracle as O
+    with threadpool_limits(1):
+        return O.fcc_tdoa(x, N, hop, tau_max, B.D, basis=B)
+
+
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(rec, tau_max, D, workers=None, runs=3, chunk=256):
+    """The FP64 NumPy oracle (STFT, PHAT, folded projection, expansion,
+    argmax) over every frame of the benchmark recording on the host's cores:
+    runs of `chunk` frames spread over a pool of worker processes (spawned, so
+    none of them touches the GPU), one BLAS thread each; the median of `runs`
+    timed passes."""
+    import multiprocessing as mp
+    import statistics
+    import numpy as np
     import oracle.fcc_oracle as O
     T = (rec.L - rec.N) // rec.hop + 1
     P = rec.M * (rec.M - 1) // 2
-    with threadpool_limits(1):
-        B = O.fcc_basis(rec.N, tau_max, D)
-        t0 = time.perf_counter()
-        O.fcc_tdoa(rec.x, rec.N, rec.hop, tau_max, D, frames=np.arange(32), basis=B)
-        per_frame = (time.perf_counter() - t0) / 32
-        n = int(min(T, max(64, budget_s / max(per_frame, 1e-6))))
-        frames = np.arange(n)
-        t0 = time.perf_counter()
-        O.fcc_tdoa(rec.x, rec.N, rec.hop, tau_max, D, frames=frames, basis=B)
-        dt = time.perf_counter() - t0
-    return {"value": n * P / dt, "unit": "pair-frames/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {n} of {T} frames x {P} pairs of the benchmark recording, "
-                      f"FP64 NumPy oracle fcc_tdoa (STFT, PHAT, folded projection, D={D}, argmax), "
-                      f"one thread, {dt:.1f} s"}
+    avail = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    if workers is None:
+        workers = min(16, avail)          # one GPU's share of a shared host
+    B = O.fcc_basis(rec.N, tau_max, D)
+    jobs = []
+    for f0 in range(0, T, chunk):
+        f1 = min(T, f0 + chunk)
+        jobs.append((np.ascontiguousarray(rec.x[:, f0 * rec.hop:(f1 - 1) * rec.hop + rec.N]),
+                     rec.N, rec.hop, tau_max, B))
+    ctx = mp.get_context("spawn")
+    times = []
+    with ctx.Pool(workers) as pool:
+        pool.map(_oracle_frames, jobs[:workers])          # start-up and imports, untimed
+        for _ in range(runs):
+            t0 = time.perf_counter()
+            out = pool.map(_oracle_frames, jobs, chunksize=1)
+            times.append(time.perf_counter() - t0)
+    assert sum(o.shape[0] for o in out) == T
+    dt = statistics.median(times)
+    return {"value": T * P / dt, "unit": "pair-frames/s", "cores": workers, "kind": "oracle",
+            "nproc": os.cpu_count(), "cpus_available": avail, "cpu_model": _cpu_model(),
+            "runs_s": [round(t, 3) for t in times],
+            "sample": f"all {T} frames x {P} pairs of the benchmark recording, FP64 NumPy oracle fcc_tdoa "
+                      f"(STFT, PHAT, folded projection, D={D}, expansion, argmax) in runs of {chunk} frames "
+                      f"over {workers} worker processes with one BLAS thread each; median of {runs} passes"}
 
 
 def other_paths(torch, fcc, rec, x, dev, args):
@@ -255,9 +312,9 @@ def main():
     torch.cuda.set_device(dev)
     x = torch.from_numpy(rec.x).to(dev)
 
-    def make(precision, rank, method="fcc"):
+    def make(precision, rank, method="fcc", operands="fp16"):
         plan = fcc.Plan(rec.mic_xyz, rec.fs, rec.c, frame_size=rec.N, hop=rec.hop,
-                        rank=rank, precision=precision, method=method)
+                        rank=rank, precision=precision, method=method, operands=operands)
         T = plan.num_frames(rec.L)
         ws = torch.empty(plan.workspace_bytes(T), dtype=torch.uint8, device=dev)
         out = torch.empty((T, plan.P), dtype=torch.int32, device=dev)
@@ -305,19 +362,61 @@ def main():
                 "kernels_GBs": {"stft_phat": round(kb["stft_phat"] / ms_stft / 1e6, 1),
                                 "pair": round(kb["pair"] / ms_pair / 1e6, 1)}}
 
+    # the whole step against the same peak: all algorithmic bytes of the step
+    # (audio read, spectra written and read back, lags written) over its time
+    step_bytes = kb["stft_phat"] + kb["pair"]
+    roofline["step"] = {"bytes": step_bytes, "GBs": round(step_bytes / (ms * 1e-3) / 1e9, 1),
+                        "frac": round(step_bytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    roofline["mfma_busy"] = busy_for(pair_file, workload, args.precision, args.rank)
+
+    # Cold buffers: the step's working set (audio, spectra, lags) fits the
+    # 256 MB Infinity Cache, and repeated steps on one set partly hit it.
+    # Rotating three independent sets (audio copies, workspaces, outputs)
+    # puts more than twice that cache between two uses of a set.
+    sets = [(x.clone(), torch.empty_like(ws), torch.empty_like(out)) for _ in range(3)]
+    cold_bytes = sum(a.numel() * 4 + w.numel() + o.numel() * 4 for a, w, o in sets)
+    rot = [0]
+
+    def cold_step():
+        a, w, o = sets[rot[0] % 3]
+        rot[0] += 1
+        plan.tdoa(a, out=o, workspace=w)
+
+    for _ in range(max(3, args.warmup)):
+        cold_step()
+    ms_cold = time_loop(torch, cold_step, max(3, args.steps))
+    cold = {"ms": round(ms_cold, 5), "pair_frames_per_s": round(T * P / (ms_cold * 1e-3)),
+            "sets": 3, "working_set_bytes": cold_bytes,
+            "step_GBs": round(step_bytes / (ms_cold * 1e-3) / 1e9, 1),
+            "step_frac": round(step_bytes / (ms_cold * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    del sets
+
     sweep, extras = [], {}
     if not args.no_sweep:
-        for prec, rank, method in [("fp32", 6, "fcc"), ("fp32", 11, "fcc"), ("bf16", 6, "fcc"),
-                                   ("bf16", 11, "fcc"), ("fp16", 6, "fcc"), ("fp16", 11, "fcc"),
-                                   ("fp8", 6, "fcc"), ("fp8", 11, "fcc"), ("fp32", 0, "gcc"),
-                                   ("fp16", 0, "gcc")]:
-            pl, Tq, wq, oq = make(prec, rank, method)
+        for prec, rank, method, ops in [("fp32", 6, "fcc", "fp16"), ("fp32", 11, "fcc", "fp16"),
+                                        ("bf16", 6, "fcc", "fp16"), ("bf16", 11, "fcc", "fp16"),
+                                        ("fp16", 6, "fcc", "fp16"), ("fp16", 11, "fcc", "fp16"),
+                                        ("fp8", 6, "fcc", "fp16"), ("fp8", 11, "fcc", "fp16"),
+                                        ("bf16", 6, "fcc", "storage"), ("bf16", 11, "fcc", "storage"),
+                                        ("fp8", 6, "fcc", "storage"), ("fp8", 11, "fcc", "storage"),
+                                        ("fp32", 0, "gcc", "fp16"), ("fp16", 0, "gcc", "fp16")]:
+            pl, Tq, wq, oq = make(prec, rank, method, ops)
             f = lambda: pl.tdoa(x, out=oq, workspace=wq)  # noqa: E731
             for _ in range(args.warmup):
                 f()
             msq = time_loop(torch, f, args.steps)
-            sweep.append({"method": method, "precision": prec, "rank": pl.rank,
-                          "ms": round(msq, 4), "pair_frames_per_s": round(Tq * pl.P / (msq * 1e-3))})
+            spec_q = wq[:Tq * pl.info.spectrum_bytes_per_frame].view(pl.spectrum_dtype()).view(
+                Tq, pl.M, pl.N // 2, 2)
+            g = lambda: pl.tdoa_from_spectra(spec_q, out=oq)  # noqa: E731
+            for _ in range(2):
+                g()
+            msp = time_loop(torch, g, args.steps)
+            entry = {"method": method, "precision": prec, "rank": pl.rank,
+                     "ms": round(msq, 4), "pair_frames_per_s": round(Tq * pl.P / (msq * 1e-3)),
+                     "pair_stage_ms": round(msp, 4)}
+            if method == "fcc" and prec in ("bf16", "fp8"):
+                entry["mfma_operands"] = {"fp16": "fp16", "storage": prec}[ops]
+            sweep.append(entry)
         extras = other_paths(torch, fcc, rec, x, dev, args)
         # context only, never `value`: the same step with the audio handed over
         # from pinned host memory and the lags returned to it across PCIe
@@ -338,7 +437,7 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(rec, plan.tau_max, plan.rank, args.cpu_seconds)
+        cpu = cpu_baseline(rec, plan.tau_max, plan.rank, workers=args.cpu_workers or None)
 
     line = {
         "metric": METRIC, "value": round(value), "unit": "pair-frames/s", "n_gpus": 1,
@@ -352,6 +451,7 @@ def main():
                    "precision": args.precision, "method": "fcc"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "cold_buffers": cold,
         "sweep": sweep,
         "other_paths": extras,
     }

@@ -46,3 +46,18 @@ def test_kernel_bytes_per_launch():
     spec = T * 16 * 256 * 4
     assert kb["stft_phat"] == 16 * L * 4 + spec          # audio read once, spectra written once
     assert kb["pair"] == spec + T * 120 * 4              # spectra read once, one int32 per pair-frame
+
+
+def test_busy_record_needs_matching_source():
+    assert bench.busy_for("pair_mfma.hip", "no-such-workload", "fp16", 11) is None
+
+
+def test_cpu_baseline_small(tmp_path):
+    """The CPU oracle baseline on a short recording: every frame, stated
+    cores, CPU model and a median of the passes."""
+    from gen import make_recording
+    rec = make_recording(1)                       # 1 s, 4 mics: 122 frames
+    r = bench.cpu_baseline(rec, 4, 9, workers=2, runs=3, chunk=64)
+    assert r["kind"] == "oracle" and r["cores"] == 2 and len(r["runs_s"]) == 3
+    assert r["value"] > 0 and r["cpu_model"] and r["nproc"] >= 1
+    assert "all 122 frames" in r["sample"]
