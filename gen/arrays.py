@@ -218,7 +218,7 @@ def random_signals(seed: int, M: int, L: int, kind: str = "white") -> np.ndarray
 
 def fractional_delay_frames(seed: int, count: int, M: int = 8, radius: float = 0.04,
                             fs: float = 16000.0, N: int = 512, c: float = 343.0,
-                            snr_db=(0.0, 20.0), chunk: int = 2048):
+                            snr_db=(0.0, 20.0), chunk: int = 2048, rt60=None, drr_db=(0.0, 10.0)):
     """`count` independent single-frame recordings of a circular array with
     fractional (sub-sample) propagation delays.
 
@@ -229,6 +229,12 @@ def fractional_delay_frames(seed: int, count: int, M: int = 8, radius: float = 0
     band-limited (periodic sinc) interpolation, and the middle N samples are
     kept.  Each mic gets white sensor noise at an SNR uniform in `snr_db`
     relative to its own frame power.
+
+    With rt60 = (lo, hi) seconds each mic also hears a reverberant tail: white
+    noise decaying by 60 dB over an RT60 drawn from U[lo, hi], starting one
+    sample after the direct path and wrapped onto the 2N-sample period
+    (circular convolution), scaled to a direct-to-reverberant ratio drawn
+    from U[drr_db].  The delays returned stay those of the direct path.
 
     Returns (x, delays, xyz): x [M][count * N] float32, frame e occupying
     samples [e N, (e + 1) N) (frame with hop N); delays [count][M] in samples
@@ -251,7 +257,16 @@ def fractional_delay_frames(seed: int, count: int, M: int = 8, radius: float = 0
         S[:, 0] = S[:, 0].real
         S[:, -1] = 0.0
         phase = np.exp(-2j * np.pi * f[None, None, :] * d[:, :, None] / Lp)  # [E][M][F]
-        sig = np.fft.irfft(S[:, None, :] * phase, n=Lp, axis=-1)[:, :, N // 2: N // 2 + N]
+        H = phase
+        if rt60 is not None:
+            n = np.arange(1, Lp)
+            T60 = rng.uniform(rt60[0], rt60[1], (E, M, 1)) * fs
+            tail = rng.standard_normal((E, M, Lp - 1)) * np.exp(-6.907755 * n[None, None, :] / T60)
+            drr = rng.uniform(drr_db[0], drr_db[1], (E, M, 1))
+            tail *= np.sqrt(10.0 ** (-drr / 10.0) / np.sum(tail * tail, axis=-1, keepdims=True))
+            h = np.concatenate([np.zeros((E, M, 1)), tail], axis=-1)          # starts one sample late
+            H = phase * (1.0 + np.fft.rfft(h, n=Lp, axis=-1))                  # tail follows the direct path
+        sig = np.fft.irfft(S[:, None, :] * H, n=Lp, axis=-1)[:, :, N // 2: N // 2 + N]
         p = np.mean(sig * sig, axis=-1, keepdims=True)
         snr = rng.uniform(snr_db[0], snr_db[1], (E, M, 1))
         sig = sig + rng.standard_normal(sig.shape) * np.sqrt(p * 10.0 ** (-snr / 10.0))

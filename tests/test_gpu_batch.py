@@ -147,3 +147,58 @@ def test_batch_wide_tiles(torch, fcc):
     b.tune(audio)
     for a, (g, e) in enumerate(zip(b.split(b.tdoa(audio, graph=True)), expect)):
         assert np.array_equal(g.cpu().numpy(), e), ("tuned", a)
+
+
+def test_batch_full_scale(torch, fcc):
+    """The batched workload at its stated scale: 256 arrays x 10 s (M 2-16,
+    2-10 cm, 16 / 48 kHz, N 256 / 512 / 1024, rank tau_max + 1), autotuned,
+    graph-captured.  Every array's lags equal the single-array path bit for
+    bit; four arrays spanning the frame sizes and both rates are checked
+    against the FP64 oracle on sampled frames: the single-array path's
+    correlation y on the same FP16 spectra within 5e-3, and the batch's lags
+    bit-exact where the top two values are 1e-2 max|y| apart; and the batch's
+    own lags against the FP64 oracle on the raw audio."""
+    _say("batch full scale: 256 arrays x 10 s")
+    from paper_2204_13622_amd import Plan
+    arrays = batch_arrays(4000, 256, 10.0)
+    plans = _plans(fcc, arrays, "fp16")
+    b = fcc.Batch(plans, [a["x"].shape[1] for a in arrays])
+    audio = b.pack([torch.from_numpy(a["x"]) for a in arrays])
+    units = sum(T * p.P for T, p in zip(b.frames, plans))
+    b.tune(audio)
+    out = [t.cpu().numpy().copy() for t in b.split(b.tdoa(audio, graph=True))]
+    del audio
+    print(f"{units} pair-frames in {b.info.num_classes} classes", flush=True)
+    picks = {}
+    for a, (arr, p) in enumerate(zip(arrays, plans)):
+        x = torch.from_numpy(arr["x"]).cuda()
+        assert np.array_equal(out[a], p.tdoa(x).cpu().numpy()), a
+        picks.setdefault((arr["N"], arr["fs"]), a)
+    chosen = sorted(picks.values())
+    assert len({arrays[a]["N"] for a in chosen}) == 3 and len({arrays[a]["fs"] for a in chosen}) == 2
+    rng = np.random.default_rng(4001)
+    for a in chosen[:6]:
+        p, x = plans[a], arrays[a]["x"]
+        T = b.frames[a]
+        frames = np.unique(np.concatenate([[0, T - 1], rng.choice(T, 16, replace=False)]))
+        X = O.stft(x, p.N, p.hop, frames=frames)
+        packed = Plan.pack_spectrum(O.phat(X)).astype(np.float16)
+        e = Plan.unpack_spectrum(packed.astype(np.float64))
+        R = np.stack([e[:, i] * np.conj(e[:, j]) for i, j in O.mic_pairs(p.M)], axis=1)
+        y_ref = O.fcc_corr(R, O.fcc_basis(p.N, p.tau_max, p.rank))
+        y = p.correlation(torch.from_numpy(packed).cuda().contiguous()).cpu().numpy()
+        err = corr_errors(y, y_ref)
+        rep = tdoa_report(p.tdoa_from_spectra(torch.from_numpy(packed).cuda().contiguous()).cpu().numpy(),
+                          y_ref, p.tau_max, 5e-3)
+        print(f"array {a}: M={p.M} N={p.N} fs={arrays[a]['fs']:.0f} D={p.rank} "
+              f"max rel corr err {err.max():.2e}, qualified {rep['qualified']}", flush=True)
+        assert err.max() < 5e-3
+        assert rep["mismatch_qualified"] == 0 and rep["invalid_elsewhere"] == 0, rep
+        # the batch's own lags (its own front end) against the FP64 oracle on
+        # the raw audio, at the error the single-array correlation shows there
+        y64 = O.fcc_corr(O.phat(O.cross_spectrum(X)), O.fcc_basis(p.N, p.tau_max, p.rank))
+        y_gpu = p.correlation(p.spectra(torch.from_numpy(x).cuda())).cpu().numpy()[frames]
+        e64 = corr_errors(y_gpu, y64)
+        rep_b = tdoa_report(out[a][frames], y64, p.tau_max, float(e64.max()))
+        assert e64.max() < 5e-3
+        assert rep_b["mismatch_qualified"] == 0, rep_b
