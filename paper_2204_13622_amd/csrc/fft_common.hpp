@@ -96,10 +96,25 @@ struct Radices {
 // 16 points, so the stride-16 accesses of the passes spread over the banks.
 __device__ __forceinline__ int pidx(int n) { return n + (n >> 4); }
 
+// Ordering of one exchange through LDS: a workgroup barrier, or (WAVE) when
+// every transform's lanes lie in one wavefront, a fence at wavefront scope,
+// so wavefronts run their transforms independently of each other.
+template <bool WAVE>
+__device__ __forceinline__ void exchange_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 // One LDS pass of radix R after P points have been combined; twp[r * P + k]
 // holds exp(-j 2 pi r k / (P R)).
-template <int R, int P, int NH, int LF>
+template <int R, int P, int NH, int LF, bool WAVE = false>
 __device__ __forceinline__ void lds_pass(float2* buf, const float2* twp, int lf, bool active) {
+  static_assert(!WAVE || (LF <= 64 && 64 % LF == 0), "a transform's lanes must share a wavefront");
   constexpr int NB = NH / R;          // butterflies
   constexpr int BPL = NB / LF;        // per lane
   float2 u[BPL][R];
@@ -111,7 +126,7 @@ __device__ __forceinline__ void lds_pass(float2* buf, const float2* twp, int lf,
       for (int r = 0; r < R; ++r) u[b][r] = buf[pidx(i + r * NB)];
     }
   }
-  __syncthreads();
+  exchange_sync<WAVE>();
   if (active) {
 #pragma unroll
     for (int b = 0; b < BPL; ++b) {
@@ -125,7 +140,7 @@ __device__ __forceinline__ void lds_pass(float2* buf, const float2* twp, int lf,
       for (int r = 0; r < R; ++r) buf[pidx(j + r * P)] = u[b][r];
     }
   }
-  __syncthreads();
+  exchange_sync<WAVE>();
 }
 
 }  // namespace fft

@@ -120,10 +120,11 @@ __device__ __forceinline__ void transform_samples(const float2* tw, const float2
       for (int r = 0; r < R; ++r) buf[pidx(lf * R + r)] = u[r];
     }
     between();
-    __syncthreads();
+    exchange_sync<true>();
   }
-  if constexpr (RD::R1 > 1) lds_pass<RD::R1, P1, NH, LF>(buf, tw1, lf, active);
-  if constexpr (RD::R2 > 1) lds_pass<RD::R2, P2, NH, LF>(buf, tw2, lf, active);
+  // a transform's LF lanes lie in one wavefront: only wavefront-scope ordering
+  if constexpr (RD::R1 > 1) lds_pass<RD::R1, P1, NH, LF, true>(buf, tw1, lf, active);
+  if constexpr (RD::R2 > 1) lds_pass<RD::R2, P2, NH, LF, true>(buf, tw2, lf, active);
 
   if (!active) return;
   // Real split: E = (Z(f) + Z*(NH - f)) / 2, O = (Z(f) - Z*(NH - f)) / 2j,

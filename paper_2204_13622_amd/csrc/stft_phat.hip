@@ -68,7 +68,7 @@ __global__ __launch_bounds__(kThreads) void stft_phat_kernel(
       if (next < end && (uint64_t)next * Sh::FPB + slot < (uint64_t)nfft)
         load_samples<N>(nxt, x, ld, M, hop, (uint32_t)(next * Sh::FPB + slot), lf);
     });
-    __syncthreads();   // the next block's first pass rewrites the scratch
+    exchange_sync<true>();   // the next block's first pass rewrites this wavefront's scratch
   }
 }
 
