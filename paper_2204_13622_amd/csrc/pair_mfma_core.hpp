@@ -62,10 +62,12 @@ struct OpF8 { static constexpr int slot_bytes = 2; };
 // position pos = t + lag_shift(I, 1), which puts the mirrored lag I - 1 - t
 // at 14 - pos (I is odd), so each pair reads its two rows with 16-byte loads
 // and combines them at compile-time positions.  The groups of four positions
-// of row r are swizzled by (r >> 1) & 3 against bank conflicts.
+// of row r = 16 a + b are swizzled by ((b >> 1) ^ a) & 3 against bank
+// conflicts, both where lanes run over b (expansion stores, Y_i(., j) reads)
+// and where they run over a (the transposed Y_j(., i) reads).
 __host__ __device__ constexpr int lag_shift(int I, int TT) { return TT == 1 ? (16 * TT - 1 - I) / 2 : 0; }
 __host__ __device__ constexpr int lag_row_words(int TT) { return 16 * TT; }
-__device__ __forceinline__ int lag_group(int r, int G) { return G ^ ((r >> 1) & 3); }
+__device__ __forceinline__ int lag_group(int r, int G) { return G ^ (((r >> 1) ^ (r >> 4)) & 3); }
 // Two or three lag tiles: Y[tau][i][j] at tau * kYStride + i * kYRow + j; rows
 // of 17 and a stride of 276 words keep both the writes (lanes over j) and the
 // transposed reads (lanes over i) on distinct LDS banks.  This layout holds
@@ -259,7 +261,11 @@ __device__ __forceinline__ void run_frames(const uint32_t* lds_all, uint32_t* sl
   for (; t < T; t += stride) {
     // ---- stage the frame into the slab --------------------------------------
     const typename S::T* base = spec + t * (int64_t)M * NH;
-    if (rounds >= kPre) {                       // every prefetch slot holds data: no guards
+    if (rounds >= kPre && lg_row == 6) {        // one round per microphone row (1 KB rows of
+                                                // 260 words): microphone u, immediate offsets
+#pragma unroll
+      for (int u = 0; u < kPre; ++u) *reinterpret_cast<uint4*>(slab + 4 * lane + 260 * u) = pre[u];
+    } else if (rounds >= kPre) {                // every prefetch slot holds data: no guards
 #pragma unroll
       for (int u = 0; u < kPre; ++u) {
         const int c = lane + 64 * u;
@@ -321,7 +327,7 @@ __device__ __forceinline__ void run_frames(const uint32_t* lds_all, uint32_t* sl
         // B: the rotated spectrum (a - b, a + b) of microphone `col`; the packed
         // DC / Nyquist slot holds two real bins and enters unrotated.
         const h8 sw = __builtin_shufflevector(raw, raw, 1, 0, 3, 2, 5, 4, 7, 6);
-        h8 B = raw + sw * sgn;
+        h8 B = __builtin_elementwise_fma(sw, sgn, raw);   // exact product by -1 / 1: one rounding
         if (dc_slot) {
           B[0] = raw[0];
           B[1] = raw[1];
