@@ -30,14 +30,18 @@ constexpr int kOutLag = 0, kOutCorr = 1, kOutCoef = 2, kOutParabolic = 3, kOutCo
 
 template <class S, int DB, int OUT>
 __global__ __launch_bounds__(kThreads) void pair_fold32_kernel(
-    const typename S::T* __restrict__ spec, int M, int P, int N, int I, int lag0, float inv_r,
+    const typename S::T* __restrict__ spec, int M, int P, int N, int I, int lag0, float inv_r, int overlay,
     const uint8_t* __restrict__ pairs, const float* __restrict__ pfold /*[N/4+1][DB]*/,
     const float* __restrict__ dict /*[I][2D]*/, int D, int32_t* __restrict__ tdoa,
     float* __restrict__ fout, float* __restrict__ fcoef) {
   extern __shared__ float smem[];
   const int NH = N / 2, F = NH + 1, m = N / 4;
   float2* sp = reinterpret_cast<float2*>(smem);          // [M][F]
-  float* part = smem + 2 * M * F;                        // [128][2 DB] partial sums of the second group
+  // [128][2 DB] partial sums of the second group: over the spectra when the
+  // launch asks for it (one round of pairs covers the frame, so the spectra
+  // have been read for the last time before)
+  const bool one_round = overlay != 0;
+  float* part = one_round ? smem : smem + 2 * M * F;
   const int64_t t = blockIdx.x;
   const typename S::T* src = spec + t * (int64_t)M * NH;
   for (int i = threadIdx.x; i < M * NH; i += kThreads) {
@@ -82,6 +86,8 @@ __global__ __launch_bounds__(kThreads) void pair_fold32_kernel(
         b[k] += w * xv.y;
       }
     }
+    const float2 rc = cmul_conj(ei[m], ej[m]);              // centre bin, symmetric k only
+    if (one_round) __syncthreads();                         // every lane has read the spectra
     if (half) {
       if (active)
 #pragma unroll
@@ -92,7 +98,6 @@ __global__ __launch_bounds__(kThreads) void pair_fold32_kernel(
     }
     __syncthreads();
     if (!half && active) {
-      const float2 rc = cmul_conj(ei[m], ej[m]);            // centre bin, symmetric k only
 #pragma unroll
       for (int k = 0; k < DB; ++k) {
         a[k] += part[lane_in_half * 2 * DB + 2 * k];
@@ -143,10 +148,26 @@ __global__ __launch_bounds__(kThreads) void pair_fold32_kernel(
   }
 }
 
+// LDS of one workgroup: the frame's FP32 bins and the second group's partial
+// sums.  With one round of pairs the partial sums can take the spectra's
+// place; that is done where the separate layout already fits two or more
+// workgroups per CU (N = 512: three become four, D = 11 pair stage 227 ->
+// 195 us).  Where it does not (N = 1024: one workgroup, 82 KB), the
+// overlaid layout would run two workgroups whose basis rows (16 KB, read
+// through the scalar cache) evict each other's: 0.99 -> 1.06 ms measured,
+// so the separate layout stays.
+bool fold32_overlay(int M, int N, int P, int DB) {
+  const int halfw = kThreads / 2;
+  const int pslots = P < halfw ? P : halfw;
+  const size_t spec = 2 * size_t(M) * (N / 2 + 1), part = size_t(pslots) * 2 * DB;
+  return P <= halfw && sizeof(float) * (spec + part) <= 80 * 1024;
+}
+
 size_t fold32_lds(int M, int N, int P, int DB) {
   const int halfw = kThreads / 2;
   const int pslots = P < halfw ? P : halfw;
-  return sizeof(float) * (2 * size_t(M) * (N / 2 + 1) + size_t(pslots) * 2 * DB);
+  const size_t spec = 2 * size_t(M) * (N / 2 + 1), part = size_t(pslots) * 2 * DB;
+  return sizeof(float) * (fold32_overlay(M, N, P, DB) ? (spec > part ? spec : part) : spec + part);
 }
 
 template <class S, int DB, int OUT>
@@ -161,6 +182,7 @@ hipError_t launch3(const PairArgs& a) {
   float* fout = OUT == kOutCorr ? a.y : a.tau_frac;
   hipLaunchKernelGGL(k, dim3((unsigned)a.T), dim3(kThreads), lds, a.stream,
                      static_cast<const typename S::T*>(a.spec), a.M, a.P, a.N, a.I, a.lag0, 1.f / (float)a.r,
+                     fold32_overlay(a.M, a.N, a.P, DB) ? 1 : 0,
                      a.pairs, a.pfold, a.dict, a.D, a.tdoa, fout, a.coef);
   return hipGetLastError();
 }

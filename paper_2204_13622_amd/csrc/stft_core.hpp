@@ -72,18 +72,22 @@ __device__ __forceinline__ float phat_scale(float n2) {
 // The R0 sample pairs lane lf of transform b needs for the first pass:
 // (x[2n], x[2n + 1]) for n = lf + r NB, unwindowed (b < nfft < 2^31).
 template <int N>
-__device__ __forceinline__ void load_samples(float2 (&u)[StftShape<N>::RD::R0], const float* __restrict__ x,
-                                             int64_t ld, int M, int hop, uint32_t b, int lf) {
+__device__ __forceinline__ void load_samples_at(float2 (&u)[StftShape<N>::RD::R0], const float* __restrict__ src,
+                                                int lf) {
   using RD = typename StftShape<N>::RD;
   constexpr int R = RD::R0, NB = StftShape<N>::NH / R;
-  const uint32_t t = b / (uint32_t)M;
-  const int mic = (int)(b - t * (uint32_t)M);
-  const float* src = x + (int64_t)mic * ld + (int64_t)t * hop;
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     const int n = lf + r * NB;
     u[r] = make_float2(src[2 * n], src[2 * n + 1]);
   }
+}
+template <int N>
+__device__ __forceinline__ void load_samples(float2 (&u)[StftShape<N>::RD::R0], const float* __restrict__ x,
+                                             int64_t ld, int M, int hop, uint32_t b, int lf) {
+  const uint32_t t = b / (uint32_t)M;
+  const int mic = (int)(b - t * (uint32_t)M);
+  load_samples_at<N>(u, x + (int64_t)mic * ld + (int64_t)t * hop, lf);
 }
 
 // Block-wide: the FPB transforms lblk * FPB .. + FPB - 1 (transform b is

@@ -56,17 +56,27 @@ __global__ __launch_bounds__(kThreads) void stft_phat_kernel(
   load_tables<N>(tw, tw1, tw2, twiddle);
   __syncthreads();
   const int slot = threadIdx.x / Sh::LF, lf = threadIdx.x % Sh::LF;
+  // where a block holds whole frames (M divides its transforms), a lane keeps
+  // its microphone and frame offset, and a block's first frame is uniform
+  const bool whole = Sh::FPB % M == 0;
+  const int fpb = whole ? Sh::FPB / M : 0;
+  const int mic_in = whole ? slot % M : 0, t_in = whole ? slot / M : 0;
+  const float* lane_x = x + (int64_t)mic_in * ld + (int64_t)t_in * hop;
   float2 u[Sh::RD::R0], nxt[Sh::RD::R0];
+  auto fetch = [&](int64_t blk) {
+    const uint64_t b = (uint64_t)blk * Sh::FPB + slot;
+    if (b >= (uint64_t)nfft) return;
+    if (whole) load_samples_at<N>(nxt, lane_x + blk * fpb * hop, lf);
+    else load_samples<N>(nxt, x, ld, M, hop, (uint32_t)b, lf);
+  };
   int64_t lblk = begin + local;
-  if (lblk < end && (uint64_t)lblk * Sh::FPB + slot < (uint64_t)nfft)
-    load_samples<N>(nxt, x, ld, M, hop, (uint32_t)(lblk * Sh::FPB + slot), lf);
+  if (lblk < end) fetch(lblk);
   for (; lblk < end; lblk += nx) {
 #pragma unroll
     for (int r = 0; r < Sh::RD::R0; ++r) u[r] = nxt[r];
     const int64_t next = lblk + nx;
     transform_samples<N, S, RAW>(tw, tw1, tw2, data, u, nfft, out, lblk, [&] {
-      if (next < end && (uint64_t)next * Sh::FPB + slot < (uint64_t)nfft)
-        load_samples<N>(nxt, x, ld, M, hop, (uint32_t)(next * Sh::FPB + slot), lf);
+      if (next < end) fetch(next);
     });
     exchange_sync<true>();   // the next block's first pass rewrites this wavefront's scratch
   }
