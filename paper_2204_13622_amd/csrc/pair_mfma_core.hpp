@@ -206,6 +206,161 @@ __host__ __device__ __forceinline__ int head_words(int Dp, int NH, int TT, int P
   return (shared_words(Dp, NH, TT, P, half) + 3) & ~3;
 }
 
+// The FP16 pairs of basis row 4 kb + col / 4 at a lane's four slots of K
+// step offset poff: prow points at the lane's slots of row col / 4, prow_n2
+// at that row's p(N/2) (compact rows only, where slot 0 pairs p(0) with it).
+template <bool HALF>
+__device__ __forceinline__ h8 basis_pairs(const uint32_t* prow, const _Float16* prow_n2, int prow_words, int kb,
+                                          int poff, bool dc_slot) {
+  if constexpr (HALF) {
+    typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+    const h4 v = __builtin_bit_cast(h4, *reinterpret_cast<const uint2*>(prow + 4 * kb * prow_words + poff));
+    h8 r = __builtin_shufflevector(v, v, 0, 0, 1, 1, 2, 2, 3, 3);
+    if (dc_slot) r[1] = prow_n2[2 * 4 * kb * prow_words];
+    return r;
+  } else {
+    return __builtin_bit_cast(h8, *reinterpret_cast<const uint4*>(prow + 4 * kb * prow_words + poff));
+  }
+}
+
+// One K step of the projection with FP16 operands: 16 slots (32 interleaved
+// re / im values) of every microphone.  own: this lane's four slots of
+// microphone `col` (the B operand); amic: the A rows' slots of microphone
+// (col & 3) in block 0, blocks 4 rows apart; pk(kb): the FP16 pairs of basis
+// row 4 kb + col / 4 at the lane's four slots.  ALL: every block of four
+// microphones holds one (all four run, A rows loaded first); otherwise only
+// blocks ib < nib run (rows of absent microphones have nothing to add).
+// dc_slot: the lane's first slot is the packed DC / Nyquist slot, whose two
+// real bins enter unrotated.
+template <int KB, bool ALL, class PK>
+__device__ __forceinline__ void kstep_f16(f4 (&acc)[KB][4], const uint32_t* own, const uint32_t* amic, int row,
+                                          int nib, bool dc_slot, PK&& pk_of) {
+  const h8 sgn = {-1, 1, -1, 1, -1, 1, -1, 1};
+  const h8 raw = __builtin_bit_cast(h8, *reinterpret_cast<const uint4*>(own));
+  // B: the rotated spectrum (a - b, a + b) of microphone `col`
+  const h8 sw = __builtin_shufflevector(raw, raw, 1, 0, 3, 2, 5, 4, 7, 6);
+  h8 B = __builtin_elementwise_fma(sw, sgn, raw);   // exact product by -1 / 1: one rounding
+  if (dc_slot) {
+    B[0] = raw[0];
+    B[1] = raw[1];
+  }
+  if constexpr (ALL) {
+    h8 Am[4];
+#pragma unroll
+    for (int ib = 0; ib < 4; ++ib) Am[ib] = __builtin_bit_cast(h8, *reinterpret_cast<const uint4*>(amic + 4 * ib * row));
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) {
+      const h8 pk = pk_of(kb);
+#pragma unroll
+      for (int ib = 0; ib < 4; ++ib)
+        acc[kb][ib] = __builtin_amdgcn_mfma_f32_16x16x32_f16(Am[ib] * pk, B, acc[kb][ib], 0, 0, 0);
+    }
+  } else {
+    h8 pk[KB];
+#pragma unroll
+    for (int kb = 0; kb < KB; ++kb) pk[kb] = pk_of(kb);
+#pragma unroll
+    for (int ib = 0; ib < 4; ++ib) {
+      if (ib < nib) {
+        const h8 Am = __builtin_bit_cast(h8, *reinterpret_cast<const uint4*>(amic + 4 * ib * row));
+#pragma unroll
+        for (int kb = 0; kb < KB; ++kb)
+          acc[kb][ib] = __builtin_amdgcn_mfma_f32_16x16x32_f16(Am * pk[kb], B, acc[kb][ib], 0, 0, 0);
+      }
+    }
+  }
+}
+
+// Expansion of one block of four microphones: Y_i(tau, j) = sum_k G(tau, k)
+// H_k(i, j) for i = 4 ib + q.  h[kb] holds the block's projection tile kb
+// (register q of lane (g, col): H_{4kb+g}(4ib+q, col)), gx the A operands
+// G(position 16 tt + col, k = 4 kb + g); the outputs of lane (g, col) are
+// positions 16 tt + 4 g .. + 3 of row 16 i + col of the lag rows in ybuf.
+template <int KB, int TT>
+__device__ __forceinline__ void expand_block(const f4 (&h)[KB], const float (&gx)[TT][KB], float* ybuf, int ib,
+                                             int g, int col, int I) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = 16 * (4 * ib + q) + col;
+#pragma unroll
+    for (int tt = 0; tt < TT; ++tt) {
+      f4 Y = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kb = 0; kb < KB; ++kb) Y = __builtin_amdgcn_mfma_f32_16x16x4f32(gx[tt][kb], h[kb][q], Y, 0, 0, 0);
+      if constexpr (TT == 1) {
+        *reinterpret_cast<f4*>(ybuf + r * lag_row_words(1) + 4 * lag_group(r, g)) = Y;
+      } else {
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) {  // rows tau >= I are padding: all go to row I, never read
+          const int tau = 16 * tt + 4 * g + qq;
+          ybuf[(tau < I ? tau : I) * kYStride + (4 * ib + q) * kYRow + col] = Y[qq];
+        }
+      }
+    }
+  }
+}
+
+// One pair (i, j) of output row `orow`: y_ij(t) = Y_i(t, j) + Y_j(I - 1 - t, i)
+// from the lag rows, then the first index of the largest value (tdoa, as a
+// lag relative to lag0) or every lag (yout).
+template <int TT, bool WRITE_Y>
+__device__ __forceinline__ void pair_peak(const float* ybuf, uint32_t ij, int I, int lag0, int64_t orow,
+                                          int32_t* __restrict__ tdoa, float* __restrict__ yout) {
+  const int i = ij & 0xff, j = ij >> 8;
+  if constexpr (TT == 1) {
+    const int sh = lag_shift(I, 1);
+    const int r1 = 16 * i + j, r2 = 16 * j + i;
+    float v1[16], v2[16];
+#pragma unroll
+    for (int G = 0; G < 4; ++G) {
+      const f4 a = *reinterpret_cast<const f4*>(ybuf + r1 * lag_row_words(1) + 4 * lag_group(r1, G));
+      const f4 c = *reinterpret_cast<const f4*>(ybuf + r2 * lag_row_words(1) + 4 * lag_group(r2, G));
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        v1[4 * G + e] = a[e];
+        v2[4 * G + e] = c[e];
+      }
+    }
+    float best = -__builtin_inff();
+    int bi = 0;
+#pragma unroll
+    for (int pos = 0; pos < 15; ++pos) {
+      const float y = v1[pos] + v2[14 - pos];
+      const bool valid = pos >= sh && pos < sh + I;
+      if (valid && y > best) {
+        best = y;
+        bi = pos;
+      }
+      if (WRITE_Y && valid) yout[orow * I + (pos - sh)] = y;
+    }
+    if (!WRITE_Y) tdoa[orow] = bi - sh - lag0;
+  } else {
+    const float* ya = ybuf + i * kYRow + j;
+    const float* yb = ybuf + (I - 1) * kYStride + j * kYRow + i;
+    // all lag reads issue together (compile-time bound, guarded), then the
+    // first-index argmax
+    float y[16 * TT];
+#pragma unroll
+    for (int tau = 0; tau < 16 * TT; ++tau) y[tau] = tau < I ? ya[tau * kYStride] + yb[-tau * kYStride] : 0.f;
+    float best = y[0];
+    int bi = 0;
+#pragma unroll
+    for (int tau = 1; tau < 16 * TT; ++tau) {
+      if (tau < I && y[tau] > best) {
+        best = y[tau];
+        bi = tau;
+      }
+    }
+    if (WRITE_Y) {
+#pragma unroll
+      for (int tau = 0; tau < 16 * TT; ++tau)
+        if (tau < I) yout[orow * I + tau] = y[tau];
+    } else {
+      tdoa[orow] = bi - lag0;
+    }
+  }
+}
+
 // One wavefront runs the frames t = first, first + step, ... < end of one
 // array (spectra `spec`, outputs `tdoa` / `yout` indexed t * P + p), with the
 // array's tables already in LDS and `slab` its own LDS slab.
@@ -249,7 +404,6 @@ __device__ __forceinline__ void run_frames(const uint32_t* lds_all, uint32_t* sl
   };
   if (t < T) prefetch(t);
 
-  const h8 sgn = {-1, 1, -1, 1, -1, 1, -1, 1};
   const h2 sgn2 = {-1, 1};
   const int nsteps = NH / 16;
   const int nib = (M + 3) >> 2;                 // blocks of four microphones holding any microphone
@@ -303,17 +457,8 @@ __device__ __forceinline__ void run_frames(const uint32_t* lds_all, uint32_t* sl
     const uint32_t* amic = slab + (col & 3) * row + lane_words * g;
     const uint32_t* prow = ptab + (col >> 2) * prow_words + (HALF ? 2 : 4) * g;
     const _Float16* prow_n2 = reinterpret_cast<const _Float16*>(ptab + (col >> 2) * prow_words + NH / 2);
-    // the FP16 pairs of basis row 4 kb + col / 4 at this lane's four slots
     auto load_pk = [&](int kb, int poff, bool dc_slot) -> h8 {
-      if constexpr (HALF) {
-        typedef _Float16 h4 __attribute__((ext_vector_type(4)));
-        const h4 v = __builtin_bit_cast(h4, *reinterpret_cast<const uint2*>(prow + 4 * kb * prow_words + poff));
-        h8 r = __builtin_shufflevector(v, v, 0, 0, 1, 1, 2, 2, 3, 3);
-        if (dc_slot) r[1] = prow_n2[2 * 4 * kb * prow_words];        // slot 0 pairs p(0) with p(N/2)
-        return r;
-      } else {
-        return __builtin_bit_cast(h8, *reinterpret_cast<const uint4*>(prow + 4 * kb * prow_words + poff));
-      }
+      return basis_pairs<HALF>(prow, prow_n2, prow_words, kb, poff, dc_slot);
     };
     // one K step: 16 slots (32 interleaved re / im values).  ALL: every block
     // of four microphones holds one (all four blocks run, A rows loaded
@@ -322,42 +467,8 @@ __device__ __forceinline__ void run_frames(const uint32_t* lds_all, uint32_t* sl
     // offset in the slab, poff in the basis rows (FP16 or BF16 pairs).
     auto kstep = [&](auto all, int soff, int poff, bool dc_slot) {
       if constexpr (kF16) {
-        const uint4 rw = *reinterpret_cast<const uint4*>(own + soff);
-        const h8 raw = __builtin_bit_cast(h8, rw);
-        // B: the rotated spectrum (a - b, a + b) of microphone `col`; the packed
-        // DC / Nyquist slot holds two real bins and enters unrotated.
-        const h8 sw = __builtin_shufflevector(raw, raw, 1, 0, 3, 2, 5, 4, 7, 6);
-        h8 B = __builtin_elementwise_fma(sw, sgn, raw);   // exact product by -1 / 1: one rounding
-        if (dc_slot) {
-          B[0] = raw[0];
-          B[1] = raw[1];
-        }
-        if constexpr (decltype(all)::value) {
-          h8 Am[4];
-#pragma unroll
-          for (int ib = 0; ib < 4; ++ib)
-            Am[ib] = __builtin_bit_cast(h8, *reinterpret_cast<const uint4*>(amic + 4 * ib * row + soff));
-#pragma unroll
-          for (int kb = 0; kb < KB; ++kb) {
-            const h8 pk = load_pk(kb, poff, dc_slot);
-#pragma unroll
-            for (int ib = 0; ib < 4; ++ib)
-              acc[kb][ib] = __builtin_amdgcn_mfma_f32_16x16x32_f16(Am[ib] * pk, B, acc[kb][ib], 0, 0, 0);
-          }
-        } else {
-          h8 pk[KB];
-#pragma unroll
-          for (int kb = 0; kb < KB; ++kb) pk[kb] = load_pk(kb, poff, dc_slot);
-#pragma unroll
-          for (int ib = 0; ib < 4; ++ib) {
-            if (ib < nib) {
-              const h8 Am = __builtin_bit_cast(h8, *reinterpret_cast<const uint4*>(amic + 4 * ib * row + soff));
-#pragma unroll
-              for (int kb = 0; kb < KB; ++kb)
-                acc[kb][ib] = __builtin_amdgcn_mfma_f32_16x16x32_f16(Am * pk[kb], B, acc[kb][ib], 0, 0, 0);
-            }
-          }
-        }
+        kstep_f16<KB, decltype(all)::value>(acc, own + soff, amic + soff, row, nib, dc_slot,
+                                            [&](int kb) { return load_pk(kb, poff, dc_slot); });
       } else if constexpr (kBF16) {
         // BF16 pairs: the rotation and the products in FP32, rounded to BF16
         const uint4 rw = *reinterpret_cast<const uint4*>(own + soff);
@@ -467,88 +578,15 @@ __device__ __forceinline__ void run_frames(const uint32_t* lds_all, uint32_t* sl
 #pragma unroll
     for (int ib = 0; ib < 4; ++ib) {
       if (ib >= nib) continue;                  // rows i >= M are never read
+      f4 h[KB];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int r = 16 * (4 * ib + q) + col;
-#pragma unroll
-        for (int tt = 0; tt < TT; ++tt) {
-          f4 Y = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-          for (int kb = 0; kb < KB; ++kb)
-            Y = __builtin_amdgcn_mfma_f32_16x16x4f32(gx[tt][kb], acc[kb][ib][q], Y, 0, 0, 0);
-          if constexpr (TT == 1) {
-            *reinterpret_cast<f4*>(ybuf + r * lag_row_words(1) + 4 * lag_group(r, g)) = Y;
-          } else {
-#pragma unroll
-            for (int qq = 0; qq < 4; ++qq) {  // rows tau >= I are padding: all go to row I, never read
-              const int tau = 16 * tt + 4 * g + qq;
-              ybuf[(tau < I ? tau : I) * kYStride + (4 * ib + q) * kYRow + col] = Y[qq];
-            }
-          }
-        }
-      }
+      for (int kb = 0; kb < KB; ++kb) h[kb] = acc[kb][ib];
+      expand_block<KB, TT>(h, gx, ybuf, ib, g, col, I);
     }
     wave_sync();
 
     // ---- per pair: y_ij(t) = Y_i(t, j) + Y_j(I - 1 - t, i); first-index argmax
-    for (int p = lane; p < P; p += 64) {
-      const uint32_t ij = psh[p];
-      const int i = ij & 0xff, j = ij >> 8;
-      const int64_t orow = t * P + p;
-      if constexpr (TT == 1) {
-        const int sh = lag_shift(I, 1);
-        const int r1 = 16 * i + j, r2 = 16 * j + i;
-        float v1[16], v2[16];
-#pragma unroll
-        for (int G = 0; G < 4; ++G) {
-          const f4 a = *reinterpret_cast<const f4*>(ybuf + r1 * lag_row_words(1) + 4 * lag_group(r1, G));
-          const f4 c = *reinterpret_cast<const f4*>(ybuf + r2 * lag_row_words(1) + 4 * lag_group(r2, G));
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            v1[4 * G + e] = a[e];
-            v2[4 * G + e] = c[e];
-          }
-        }
-        float best = -__builtin_inff();
-        int bi = 0;
-#pragma unroll
-        for (int pos = 0; pos < 15; ++pos) {
-          const float y = v1[pos] + v2[14 - pos];
-          const bool valid = pos >= sh && pos < sh + I;
-          if (valid && y > best) {
-            best = y;
-            bi = pos;
-          }
-          if (WRITE_Y && valid) yout[orow * I + (pos - sh)] = y;
-        }
-        if (!WRITE_Y) tdoa[orow] = bi - sh - lag0;
-      } else {
-        const float* ya = ybuf + i * kYRow + j;
-        const float* yb = ybuf + (I - 1) * kYStride + j * kYRow + i;
-        // all lag reads issue together (compile-time bound, guarded), then the
-        // first-index argmax
-        float y[16 * TT];
-#pragma unroll
-        for (int tau = 0; tau < 16 * TT; ++tau)
-          y[tau] = tau < I ? ya[tau * kYStride] + yb[-tau * kYStride] : 0.f;
-        float best = y[0];
-        int bi = 0;
-#pragma unroll
-        for (int tau = 1; tau < 16 * TT; ++tau) {
-          if (tau < I && y[tau] > best) {
-            best = y[tau];
-            bi = tau;
-          }
-        }
-        if (WRITE_Y) {
-#pragma unroll
-          for (int tau = 0; tau < 16 * TT; ++tau)
-            if (tau < I) yout[orow * I + tau] = y[tau];
-        } else {
-          tdoa[orow] = bi - lag0;
-        }
-      }
-    }
+    for (int p = lane; p < P; p += 64) pair_peak<TT, WRITE_Y>(ybuf, psh[p], I, lag0, t * P + p, tdoa, yout);
     wave_sync();   // the slab is rewritten by the next frame
   }
 }

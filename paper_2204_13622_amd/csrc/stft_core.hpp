@@ -90,24 +90,21 @@ __device__ __forceinline__ void load_samples(float2 (&u)[StftShape<N>::RD::R0], 
   load_samples_at<N>(u, x + (int64_t)mic * ld + (int64_t)t * hop, lf);
 }
 
-// Block-wide: the FPB transforms lblk * FPB .. + FPB - 1 (transform b is
-// microphone b % M of frame b / M; those at or past nfft idle; nfft < 2^31),
-// given the first pass's samples of this lane's transform in `u` (loaded by
-// load_samples; ignored where inactive).  Tables in LDS already; `data` is
-// the block's transform scratch.  `between` runs after the first pass has
-// stored its outputs (a persistent caller issues its next loads there).
-template <int N, class S, bool RAW, class Between>
-__device__ __forceinline__ void transform_samples(const float2* tw, const float2* tw1, const float2* tw2,
-                                                  float2* data, float2 (&u)[StftShape<N>::RD::R0], int64_t nfft,
-                                                  typename S::T* __restrict__ out, int64_t lblk,
-                                                  Between&& between) {
+// One lane's share of one transform, given the first pass's samples of this
+// lane in `u` (ignored where inactive): window, first pass in registers, the
+// LDS passes in the transform's scratch `buf`, then the real split and, unless
+// RAW, PHAT.  `between` runs on every lane once the first pass has stored its
+// outputs (a persistent caller issues its next loads there); `emit(f, X)`
+// takes each output slot f of this lane, slot 0 packing the real bins 0 and
+// N/2.  Inactive lanes only take part in the wavefront-scope orderings (a
+// transform's lanes share a wavefront).
+template <int N, bool RAW, class Between, class Emit>
+__device__ __forceinline__ void transform_lane(const float2* tw, const float2* tw1, const float2* tw2, float2* buf,
+                                               float2 (&u)[StftShape<N>::RD::R0], bool active, int lf,
+                                               Between&& between, Emit&& emit) {
   using Sh = StftShape<N>;
   using RD = typename Sh::RD;
-  constexpr int NH = Sh::NH, LF = Sh::LF, FPB = Sh::FPB, NHP = Sh::NHP, P1 = Sh::P1, P2 = Sh::P2;
-  const int slot = threadIdx.x / LF, lf = threadIdx.x % LF;
-  const uint32_t b = (uint32_t)lblk * FPB + slot;   // = t * M + m
-  const bool active = b < (uint64_t)nfft;
-  float2* buf = data + slot * NHP;
+  constexpr int NH = Sh::NH, LF = Sh::LF, P1 = Sh::P1, P2 = Sh::P2;
   const float2* win = tw;                          // window pairs
   const float2* wsp = tw + NH;                     // W^f, f = 0 .. NH / 2
   // first pass: radix R0 on the windowed samples, no twiddles (p = 1)
@@ -126,7 +123,6 @@ __device__ __forceinline__ void transform_samples(const float2* tw, const float2
     between();
     exchange_sync<true>();
   }
-  // a transform's LF lanes lie in one wavefront: only wavefront-scope ordering
   if constexpr (RD::R1 > 1) lds_pass<RD::R1, P1, NH, LF, true>(buf, tw1, lf, active);
   if constexpr (RD::R2 > 1) lds_pass<RD::R2, P2, NH, LF, true>(buf, tw2, lf, active);
 
@@ -138,7 +134,6 @@ __device__ __forceinline__ void transform_samples(const float2* tw, const float2
   // every lane); f = 0 is the DC / Nyquist slot, done after the loop by the
   // lanes with lf = 0, which also take the centre bin NH / 2 (its own mirror).
   constexpr float h = RAW ? 0.5f : 1.f;
-  typename S::T* dst = out + (int64_t)b * NH;
   constexpr int kIters = (NH / 2 + LF - 1) / LF;
 #pragma unroll
   for (int k = 0; k < kIters; ++k) {
@@ -152,26 +147,46 @@ __device__ __forceinline__ void transform_samples(const float2* tw, const float2
     const float2 Xa = cadd(e, wo);
     const float2 Xb = make_float2(e.x - wo.x, wo.y - e.y);
     if (RAW) {
-      dst[f] = spec_encode<S>(Xa);
-      dst[NH - f] = spec_encode<S>(Xb);
+      emit(f, Xa);
+      emit(NH - f, Xb);
     } else {
       const float sa = phat_scale(Xa.x * Xa.x + Xa.y * Xa.y);
       const float sb = phat_scale(Xb.x * Xb.x + Xb.y * Xb.y);
-      dst[f] = spec_encode<S>(make_float2(Xa.x * sa, Xa.y * sa));
-      dst[NH - f] = spec_encode<S>(make_float2(Xb.x * sb, Xb.y * sb));
+      emit(f, make_float2(Xa.x * sa, Xa.y * sa));
+      emit(NH - f, make_float2(Xb.x * sb, Xb.y * sb));
     }
   }
   if (lf == 0) {
     // X(0) = Re Z(0) + Im Z(0), X(N/2) = Re Z(0) - Im Z(0); both real
     const float2 z0 = buf[0];
-    if (RAW) dst[0] = spec_encode<S>(make_float2(z0.x + z0.y, z0.x - z0.y));
-    else dst[0] = spec_encode<S>(make_float2(phat_real(z0.x + z0.y), phat_real(z0.x - z0.y)));
+    if (RAW) emit(0, make_float2(z0.x + z0.y, z0.x - z0.y));
+    else emit(0, make_float2(phat_real(z0.x + z0.y), phat_real(z0.x - z0.y)));
     // centre: E = Re Z(NH/2), O = Im Z(NH/2), X = E + W^(NH/2) O
     const float2 zc = buf[pidx(NH / 2)];
     const float2 wc = wsp[NH / 2];
     const float2 Xc = make_float2(zc.x + wc.x * zc.y, wc.y * zc.y);
-    dst[NH / 2] = spec_encode<S>(RAW ? Xc : phat_complex(Xc));
+    emit(NH / 2, RAW ? Xc : phat_complex(Xc));
   }
+}
+
+// Block-wide: the FPB transforms lblk * FPB .. + FPB - 1 (transform b is
+// microphone b % M of frame b / M; those at or past nfft idle; nfft < 2^31),
+// given the first pass's samples of this lane's transform in `u` (loaded by
+// load_samples; ignored where inactive).  Tables in LDS already; `data` is
+// the block's transform scratch.  `between` runs after the first pass has
+// stored its outputs (a persistent caller issues its next loads there).
+template <int N, class S, bool RAW, class Between>
+__device__ __forceinline__ void transform_samples(const float2* tw, const float2* tw1, const float2* tw2,
+                                                  float2* data, float2 (&u)[StftShape<N>::RD::R0], int64_t nfft,
+                                                  typename S::T* __restrict__ out, int64_t lblk,
+                                                  Between&& between) {
+  using Sh = StftShape<N>;
+  constexpr int NH = Sh::NH, LF = Sh::LF, FPB = Sh::FPB, NHP = Sh::NHP;
+  const int slot = threadIdx.x / LF, lf = threadIdx.x % LF;
+  const uint32_t b = (uint32_t)lblk * FPB + slot;   // = t * M + m
+  typename S::T* dst = out + (int64_t)b * NH;
+  transform_lane<N, RAW>(tw, tw1, tw2, data + slot * NHP, u, b < (uint64_t)nfft, lf, between,
+                         [&](int f, float2 v) { dst[f] = spec_encode<S>(v); });
 }
 
 // Block-wide: the FPB transforms lblk * FPB .. + FPB - 1, samples loaded here.
