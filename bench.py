@@ -86,7 +86,8 @@ def kernel_bytes(plan, L, T):
 # every source file a kernel's code lives in
 KERNEL_SOURCES = {
     "stft_phat.hip": ("stft_phat.hip", "stft_core.hpp", "fft_common.hpp", "device_common.hpp"),
-    "pair_mfma.hip": ("pair_mfma.hip", "pair_mfma_core.hpp", "device_common.hpp"),
+    "pair_mfma.hip": ("pair_mfma.hip", "pair_mfma_f16.hip", "pair_mfma_launch.hpp", "pair_mfma_core.hpp",
+                      "device_common.hpp"),
     "pair_fold32.hip": ("pair_fold32.hip", "device_common.hpp"),
 }
 
