@@ -2,11 +2,15 @@
 // (Sec. 4: eq. 8 fold, eq. 9 projection, y = 2 Re{U z}, argmax of Sec. 2).
 //
 // One workgroup per frame.  The frame's whitened spectra are unpacked to
-// FP32 bins 0 .. N/2 in LDS.  Lanes own pairs; the folded bins f < N/4 are
-// split between two groups of wavefronts, so within a wavefront every lane
-// visits the same bin and the basis values p_hat_k(f) are wavefront-uniform
-// (one scalar load of a contiguous row of the transposed table, no LDS
-// traffic).  Per bin a lane forms
+// FP32 bins in LDS as folded pairs: for the folded bins f of a chunk, one
+// row per microphone holds e(f), then e(N/2 - f), then the centre bin N/4.
+// Lanes own pairs; the folded bins f < N/4 of each chunk are split between
+// two groups of wavefronts, so within a wavefront every lane visits the same
+// bin and the basis values p_hat_k(f) are wavefront-uniform (one scalar load
+// of a contiguous row of the transposed table, no LDS traffic).  Frames whose
+// bins would leave a CU one workgroup (N = 1024) are staged in two chunks of
+// folded bins, one after the other, so the LDS holds half the frame.  Per bin
+// a lane forms
 //   R(f) = e_i(f) e_j(f)^*,  R(N/2 - f),  x_s = R(f) + R(N/2 - f),  x_d = R(f) - R(N/2 - f)
 // and accumulates z_k += p_hat_k(f) x_s (symmetric k) or p_hat_k(f) x_d
 // (antisymmetric k).  The second group leaves its partial coefficients in
@@ -28,65 +32,87 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kOutLag = 0, kOutCorr = 1, kOutCoef = 2, kOutParabolic = 3, kOutCoefParabolic = 4;
 
-template <class S, int DB, int OUT>
+template <class S, int DB, int OUT, int NC>
 __global__ __launch_bounds__(kThreads) void pair_fold32_kernel(
     const typename S::T* __restrict__ spec, int M, int P, int N, int I, int lag0, float inv_r, int overlay,
     const uint8_t* __restrict__ pairs, const float* __restrict__ pfold /*[N/4+1][DB]*/,
     const float* __restrict__ dict /*[I][2D]*/, int D, int32_t* __restrict__ tdoa,
     float* __restrict__ fout, float* __restrict__ fcoef) {
   extern __shared__ float smem[];
-  const int NH = N / 2, F = NH + 1, m = N / 4;
-  float2* sp = reinterpret_cast<float2*>(smem);          // [M][F]
+  const int NH = N / 2, m = N / 4;
+  const int mc = m / NC, Fc = 2 * mc + 1;                 // folded bins per chunk, row length
+  float2* sp = reinterpret_cast<float2*>(smem);          // [M][Fc]: e(f0 + q), e(NH - f0 - q), e(m)
   // [128][2 DB] partial sums of the second group: over the spectra when the
   // launch asks for it (one round of pairs covers the frame, so the spectra
   // have been read for the last time before)
   const bool one_round = overlay != 0;
-  float* part = one_round ? smem : smem + 2 * M * F;
+  float* part = one_round ? smem : smem + 2 * M * Fc;
   const int64_t t = blockIdx.x;
   const typename S::T* src = spec + t * (int64_t)M * NH;
-  for (int i = threadIdx.x; i < M * NH; i += kThreads) {
-    const int mic = i / NH, f = i - mic * NH;
-    const float2 v = spec_decode<S>(src[i]);
-    if (f == 0) {
-      sp[mic * F] = make_float2(v.x, 0.f);
-      sp[mic * F + NH] = make_float2(v.y, 0.f);
-    } else {
-      sp[mic * F + f] = v;
+  // chunk c: folded bins f0 = c mc .. f0 + mc - 1 (the packed slot 0 holds
+  // the real bins 0 and N/2)
+  auto stage = [&](int c) {
+    const int f0 = c * mc;
+    const int lg = 31 - __builtin_clz(mc);               // mc is a power of two
+    for (int x = threadIdx.x; x < M * mc; x += kThreads) {
+      const int mic = x >> lg, q = x & (mc - 1), f = f0 + q;
+      const typename S::T* row = src + mic * NH;
+      float2 lo = spec_decode<S>(row[f]);
+      float2 hi = spec_decode<S>(row[f == 0 ? 0 : NH - f]);
+      if (f == 0) {
+        lo.y = 0.f;
+        hi = make_float2(hi.y, 0.f);
+      }
+      sp[mic * Fc + q] = lo;
+      sp[mic * Fc + mc + q] = hi;
     }
+    for (int mic = threadIdx.x; mic < M; mic += kThreads) sp[mic * Fc + 2 * mc] = spec_decode<S>(src[mic * NH + m]);
+  };
+  if constexpr (NC == 1) {
+    stage(0);
+    __syncthreads();
   }
-  __syncthreads();
 
-  // lanes of the two halves: wavefronts [0, W/2) take bins [0, m/2), the rest [m/2, m)
+  // lanes of the two halves: wavefronts [0, W/2) take the first half of each
+  // chunk's folded bins, the rest the second half
   constexpr int W = kThreads / 64;
   const int wave = threadIdx.x >> 6;
   const int half = __builtin_amdgcn_readfirstlane(wave >= W / 2 ? 1 : 0);   // wavefront-uniform
   const int lane_in_half = threadIdx.x - half * (kThreads / 2);
-  const int f0 = half ? m / 2 : 0, f1 = half ? m : m / 2;
+  const int q0 = half ? mc / 2 : 0, q1 = half ? mc : mc / 2;
 
   for (int pbase = 0; pbase < P; pbase += kThreads / 2) {
     const int p = pbase + lane_in_half;
     const bool active = p < P;
     const int i = active ? pairs[2 * p] : 0, j = active ? pairs[2 * p + 1] : 0;
-    const float2* ei = sp + i * F;
-    const float2* ej = sp + j * F;
+    const float2* ei = sp + i * Fc;
+    const float2* ej = sp + j * Fc;
     float a[DB], b[DB];
 #pragma unroll
     for (int k = 0; k < DB; ++k) a[k] = b[k] = 0.f;
+    for (int c = 0; c < NC; ++c) {
+      if constexpr (NC > 1) {                               // one round of pairs (P <= 128)
+        if (c > 0) __syncthreads();                         // every lane has read chunk c - 1
+        stage(c);
+        __syncthreads();
+      }
+      const float* pc = pfold + c * mc * DB;
 #pragma unroll 2
-    for (int f = f0; f < f1; ++f) {
-      const float2 r1 = cmul_conj(ei[f], ej[f]);
-      const float2 r2 = cmul_conj(ei[NH - f], ej[NH - f]);
-      const float2 xs = cadd(r1, r2), xd = csub(r1, r2);
-      const float* pf = pfold + f * DB;                   // one contiguous, wavefront-uniform row
+      for (int q = q0; q < q1; ++q) {
+        const float2 r1 = cmul_conj(ei[q], ej[q]);
+        const float2 r2 = cmul_conj(ei[mc + q], ej[mc + q]);
+        const float2 xs = cadd(r1, r2), xd = csub(r1, r2);
+        const float* pf = pc + q * DB;                      // one contiguous, wavefront-uniform row
 #pragma unroll
-      for (int k = 0; k < DB; ++k) {
-        const float w = pf[k];
-        const float2 xv = (k % 2 == 0) ? xs : xd;         // eq. (6) order: k even symmetric
-        a[k] += w * xv.x;
-        b[k] += w * xv.y;
+        for (int k = 0; k < DB; ++k) {
+          const float w = pf[k];
+          const float2 xv = (k % 2 == 0) ? xs : xd;         // eq. (6) order: k even symmetric
+          a[k] += w * xv.x;
+          b[k] += w * xv.y;
+        }
       }
     }
-    const float2 rc = cmul_conj(ei[m], ej[m]);              // centre bin, symmetric k only
+    const float2 rc = cmul_conj(ei[2 * mc], ej[2 * mc]);    // centre bin, symmetric k only
     if (one_round) __syncthreads();                         // every lane has read the spectra
     if (half) {
       if (active)
@@ -156,23 +182,38 @@ __global__ __launch_bounds__(kThreads) void pair_fold32_kernel(
 // overlaid layout would run two workgroups whose basis rows (16 KB, read
 // through the scalar cache) evict each other's: 0.99 -> 1.06 ms measured,
 // so the separate layout stays.
+//
+// Chunks: a frame whose bins and partial sums exceed 64 KB (N = 1024: 82 KB,
+// one workgroup per CU) is staged in two chunks of folded bins when one round
+// of pairs covers it; the LDS then holds half the frame.
+int fold32_chunks(int M, int N, int P, int DB) {
+  const int halfw = kThreads / 2;
+  const int pslots = P < halfw ? P : halfw;
+  const size_t whole = sizeof(float) * (2 * size_t(M) * (N / 2 + 1) + size_t(pslots) * 2 * DB);
+  return (P <= halfw && N >= 64 && whole > 64 * 1024) ? 2 : 1;
+}
+
+static size_t fold32_spec_floats(int M, int N, int P, int DB) {
+  return 2 * size_t(M) * (2 * (N / 4 / fold32_chunks(M, N, P, DB)) + 1);
+}
+
 bool fold32_overlay(int M, int N, int P, int DB) {
   const int halfw = kThreads / 2;
   const int pslots = P < halfw ? P : halfw;
-  const size_t spec = 2 * size_t(M) * (N / 2 + 1), part = size_t(pslots) * 2 * DB;
+  const size_t spec = fold32_spec_floats(M, N, P, DB), part = size_t(pslots) * 2 * DB;
   return P <= halfw && sizeof(float) * (spec + part) <= 80 * 1024;
 }
 
 size_t fold32_lds(int M, int N, int P, int DB) {
   const int halfw = kThreads / 2;
   const int pslots = P < halfw ? P : halfw;
-  const size_t spec = 2 * size_t(M) * (N / 2 + 1), part = size_t(pslots) * 2 * DB;
+  const size_t spec = fold32_spec_floats(M, N, P, DB), part = size_t(pslots) * 2 * DB;
   return sizeof(float) * (fold32_overlay(M, N, P, DB) ? (spec > part ? spec : part) : spec + part);
 }
 
-template <class S, int DB, int OUT>
-hipError_t launch3(const PairArgs& a) {
-  auto k = pair_fold32_kernel<S, DB, OUT>;
+template <class S, int DB, int OUT, int NC>
+hipError_t launch4(const PairArgs& a) {
+  auto k = pair_fold32_kernel<S, DB, OUT, NC>;
   const size_t lds = fold32_lds(a.M, a.N, a.P, DB);
   if (lds > 64 * 1024) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k),
@@ -185,6 +226,11 @@ hipError_t launch3(const PairArgs& a) {
                      fold32_overlay(a.M, a.N, a.P, DB) ? 1 : 0,
                      a.pairs, a.pfold, a.dict, a.D, a.tdoa, fout, a.coef);
   return hipGetLastError();
+}
+
+template <class S, int DB, int OUT>
+hipError_t launch3(const PairArgs& a) {
+  return fold32_chunks(a.M, a.N, a.P, DB) == 2 ? launch4<S, DB, OUT, 2>(a) : launch4<S, DB, OUT, 1>(a);
 }
 
 template <class S, int DB>
