@@ -7,10 +7,9 @@
 // Lanes own pairs; the folded bins f < N/4 of each chunk are split between
 // two groups of wavefronts, so within a wavefront every lane visits the same
 // bin and the basis values p_hat_k(f) are wavefront-uniform (one scalar load
-// of a contiguous row of the transposed table, no LDS traffic).  Frames whose
-// bins would leave a CU one workgroup (N = 1024) are staged in two chunks of
-// folded bins, one after the other, so the LDS holds half the frame.  Per bin
-// a lane forms
+// of a contiguous row of the transposed table, no LDS traffic).  A frame is
+// staged in chunks of folded bins, one after the other, so the LDS holds a
+// part of it and more workgroups share a CU.  Per bin a lane forms
 //   R(f) = e_i(f) e_j(f)^*,  R(N/2 - f),  x_s = R(f) + R(N/2 - f),  x_d = R(f) - R(N/2 - f)
 // and accumulates z_k += p_hat_k(f) x_s (symmetric k) or p_hat_k(f) x_d
 // (antisymmetric k).  The second group leaves its partial coefficients in
@@ -174,23 +173,23 @@ __global__ __launch_bounds__(kThreads) void pair_fold32_kernel(
   }
 }
 
-// LDS of one workgroup: the frame's FP32 bins and the second group's partial
-// sums.  With one round of pairs the partial sums can take the spectra's
-// place; that is done where the separate layout already fits two or more
-// workgroups per CU (N = 512: three become four, D = 11 pair stage 227 ->
-// 195 us).  Where it does not (N = 1024: one workgroup, 82 KB), the
-// overlaid layout would run two workgroups whose basis rows (16 KB, read
-// through the scalar cache) evict each other's: 0.99 -> 1.06 ms measured,
-// so the separate layout stays.
+// LDS of one workgroup: the FP32 bins of one chunk and the second group's
+// partial sums.  With one round of pairs the partial sums can take the
+// spectra's place once the last chunk has been read.
 //
-// Chunks: a frame whose bins and partial sums exceed 64 KB (N = 1024: 82 KB,
-// one workgroup per CU) is staged in two chunks of folded bins when one round
-// of pairs covers it; the LDS then holds half the frame.
+// Chunks: when one round of pairs covers the frame, its folded bins are
+// staged in two or four chunks, one after the other, so a workgroup's LDS
+// drops to about 20 KB and a CU runs up to eight workgroups instead of one
+// (N = 1024, whose whole frame took 82 KB) or four (N = 512).
 int fold32_chunks(int M, int N, int P, int DB) {
   const int halfw = kThreads / 2;
-  const int pslots = P < halfw ? P : halfw;
-  const size_t whole = sizeof(float) * (2 * size_t(M) * (N / 2 + 1) + size_t(pslots) * 2 * DB);
-  return (P <= halfw && N >= 64 && whole > 64 * 1024) ? 2 : 1;
+  if (P > halfw || N < 64) return 1;
+  const size_t part = sizeof(float) * size_t(P) * 2 * DB;
+  for (int nc : {1, 2, 4}) {
+    const size_t spec = sizeof(float) * 2 * size_t(M) * (2 * (N / 4 / nc) + 1);
+    if ((spec > part ? spec : part) <= 20 * 1024 || (N / 4 / nc) <= 16) return nc;
+  }
+  return 4;
 }
 
 static size_t fold32_spec_floats(int M, int N, int P, int DB) {
@@ -230,7 +229,11 @@ hipError_t launch4(const PairArgs& a) {
 
 template <class S, int DB, int OUT>
 hipError_t launch3(const PairArgs& a) {
-  return fold32_chunks(a.M, a.N, a.P, DB) == 2 ? launch4<S, DB, OUT, 2>(a) : launch4<S, DB, OUT, 1>(a);
+  switch (fold32_chunks(a.M, a.N, a.P, DB)) {
+    case 4: return launch4<S, DB, OUT, 4>(a);
+    case 2: return launch4<S, DB, OUT, 2>(a);
+    default: return launch4<S, DB, OUT, 1>(a);
+  }
 }
 
 template <class S, int DB>
