@@ -32,7 +32,10 @@ def parse_args():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--precision", default="fp16", choices=["fp32", "bf16", "fp16", "fp8"])
-    ap.add_argument("--rank", type=int, default=11)
+    ap.add_argument("--rank", type=int, default=0, help="rank D (default 11, or 15 for --workload high-rate)")
+    ap.add_argument("--workload", default="benchmark", choices=["benchmark", "high-rate"],
+                    help="benchmark: 60 s at 16 kHz, N = 512 (the headline); high-rate: 120 s at 48 kHz, "
+                         "N = 1024, for profiling that workload on its own")
     ap.add_argument("--no-sweep", action="store_true", help="skip the precision/rank/method sweep")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-workers", type=int, default=0,
@@ -308,7 +311,10 @@ def main():
     import paper_2204_13622_amd as fcc
     from gen import make_recording
 
-    rec = make_recording(2, seed=args.seed)
+    high = args.workload == "high-rate"
+    if not args.rank:
+        args.rank = 15 if high else 11
+    rec = make_recording(3 if high else 2, seed=args.seed)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     x = torch.from_numpy(rec.x).to(dev)
@@ -348,7 +354,7 @@ def main():
     ms = time_loop(torch, step, args.steps)
     value = T * P / (ms * 1e-3)
     kb = kernel_bytes(plan, rec.L, T)
-    workload = "M16-circle5cm-fs16k-N512-hop128-60s"
+    workload = "M16-circle5cm-fs48k-N1024-hop256-120s" if high else "M16-circle5cm-fs16k-N512-hop128-60s"
     dom = "pair" if ms_pair >= ms_stft else "stft_phat"
     dom_ms = ms_pair if dom == "pair" else ms_stft
     achieved = kb[dom] / (dom_ms * 1e-3) / 1e9
@@ -393,7 +399,7 @@ def main():
     del sets
 
     sweep, extras = [], {}
-    if not args.no_sweep:
+    if not args.no_sweep and not high:
         for prec, rank, method, ops in [("fp32", 6, "fcc", "fp16"), ("fp32", 11, "fcc", "fp16"),
                                         ("bf16", 6, "fcc", "fp16"), ("bf16", 11, "fcc", "fp16"),
                                         ("fp16", 6, "fcc", "fp16"), ("fp16", 11, "fcc", "fp16"),
@@ -437,17 +443,21 @@ def main():
                                     "h2d_bytes": xh.numel() * 4, "d2h_bytes": oh.numel() * 4}
 
     cpu = None
-    if not args.no_cpu:
+    if not args.no_cpu and not high:
         cpu = cpu_baseline(rec, plan.tau_max, plan.rank, workers=args.cpu_workers or None)
 
     line = {
-        "metric": METRIC, "value": round(value), "unit": "pair-frames/s", "n_gpus": 1,
+        "metric": METRIC if not high else "TDoA pair-frames/s at M=16,N=1024, 48 kHz workload (profiling mode)",
+        "value": round(value), "unit": "pair-frames/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": args.precision, "data": "synthetic",
-        "config": {"workload": "60 s recording, M=16 mics on a 5 cm-radius circle, fs=16 kHz, "
-                               "N=512 Hann frames, hop 128, tau_max=5 (I=11 lags), AR(2) gated source, "
-                               "FIR reverb RT60 0.3 s, sensor noise SNR 0-20 dB",
+        "config": {"workload": ("120 s recording, M=16 mics on a 5 cm-radius circle, fs=48 kHz, "
+                                "N=1024 Hann frames, hop 256, tau_max=14 (I=29 lags), AR(2) gated source, "
+                                "FIR reverb RT60 0.3 s, sensor noise SNR 0-20 dB") if high else
+                               ("60 s recording, M=16 mics on a 5 cm-radius circle, fs=16 kHz, "
+                                "N=512 Hann frames, hop 128, tau_max=5 (I=11 lags), AR(2) gated source, "
+                                "FIR reverb RT60 0.3 s, sensor noise SNR 0-20 dB"),
                    "frames": T, "pairs": P, "pair_frames": T * P, "rank": plan.rank,
                    "precision": args.precision, "method": "fcc"},
         "roofline": roofline,
