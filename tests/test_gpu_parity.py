@@ -587,6 +587,32 @@ def test_rank_and_size_limits(torch, fcc, M, N, tau_max, D, precision, tol):
     assert rep["mismatch_qualified"] == 0 and rep["invalid_elsewhere"] == 0, rep
 
 
+@pytest.mark.parametrize("M,N,tau_max,D", [
+    (16, 256, 5, 11),      # the whole frame in one chunk (16.5 KB of bins)
+    (16, 512, 5, 11),      # two chunks of folded bins (the benchmark shape)
+    (9, 1024, 14, 15),     # two chunks, odd microphone count
+    (16, 1024, 14, 15),    # four chunks (the 48 kHz shape)
+    (16, 2048, 14, 15),    # four chunks of 128 folded bins each (33 KB)
+    (2, 64, 1, 3),         # one pair, one chunk
+])
+def test_fold_kernel_chunks(torch, fcc, M, N, tau_max, D):
+    """FP32 pair stage (the fold kernel) against the oracle on shapes that
+    stage the frame's folded bins in one, two and four chunks."""
+    _say(f"fold chunks M={M} N={N} tau_max={tau_max} D={D}")
+    hop = N // 4
+    x = random_signals(1700 + M + N, M, N + 24 * hop)
+    p = fcc.Plan(circular_array(M, 0.05), 16000.0, frame_size=N, hop=hop, tau_max=tau_max, rank=D,
+                 precision="fp32")
+    X = O.stft(x, N, hop)
+    spec = _oracle_spec_tensor(torch, X, torch.float32)
+    y_ref = O.fcc_corr(O.phat(O.cross_spectrum(X)), O.fcc_basis(N, tau_max, D))
+    y = p.correlation(spec).cpu().numpy()
+    t = p.tdoa_from_spectra(spec).cpu().numpy()
+    assert y.shape == y_ref.shape == (25, p.P, 2 * tau_max + 1)
+    rep = _check_fp32(t, y, y_ref, tau_max)
+    print(rep, flush=True)
+
+
 # ------------------------------------------------------ coefficients (eq. 9) --
 
 def _sigma_clusters(sigma, is_sym, rel=1e-6):
