@@ -61,3 +61,18 @@ def test_cpu_baseline_small(tmp_path):
     assert r["kind"] == "oracle" and r["cores"] == 2 and len(r["runs_s"]) == 3
     assert r["value"] > 0 and r["cpu_model"] and r["nproc"] >= 1
     assert "all 122 frames" in r["sample"]
+
+
+def test_workload_option():
+    """--workload high-rate selects the 48 kHz workload for profiling; the
+    default stays the benchmark workload (rank chosen in main when 0)."""
+    old = sys.argv
+    try:
+        sys.argv = ["bench.py"]
+        a = bench.parse_args()
+        assert a.workload == "benchmark" and a.rank == 0
+        sys.argv = ["bench.py", "--workload", "high-rate", "--rank", "29"]
+        a = bench.parse_args()
+        assert a.workload == "high-rate" and a.rank == 29
+    finally:
+        sys.argv = old
